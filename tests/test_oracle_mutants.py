@@ -1,0 +1,76 @@
+"""The oracle pins catch plausible mistakes.
+
+Each case applies one textual mutation to a copy of the oracle's C source
+(a dropped term, a flipped sign, a wrong normaliser or index, a changed
+order), builds it on the CPU, and runs the pins against it: at least one pin
+must fail.  The repository's oracle itself is never modified.
+"""
+import os
+import subprocess
+
+import pytest
+
+import tests.test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "stdecomp_oracle.c")
+
+MUTANTS = {
+    "core_drops_lambda": ("double grad = -sum_rh[lin] / (double)m + lam_G * G[lin];",
+                          "double grad = -sum_rh[lin] / (double)m;"),
+    "core_wrong_average": ("double grad = -sum_rh[lin] / (double)m + lam_G * G[lin];",
+                           "double grad = -sum_rh[lin] / (double)(m + 1) + lam_G * G[lin];"),
+    "core_residual_sign": ("sum_rh[lin] += r * h;", "sum_rh[lin] -= r * h;"),
+    "row_residual_sign": ("F[jn] += -r[p] * E[(int64_t)p * Jn + jn];", "F[jn] += r[p] * E[(int64_t)p * Jn + jn];"),
+    "row_normaliser_m": ("a[jn] -= gam_A * (F[jn] / (double)c + lam_A * a[jn]);",
+                         "a[jn] -= gam_A * (F[jn] / (double)m + lam_A * a[jn]);"),
+    "row_drops_lambda": ("a[jn] -= gam_A * (F[jn] / (double)c + lam_A * a[jn]);",
+                         "a[jn] -= gam_A * (F[jn] / (double)c);"),
+    "E_wrong_index": ("E[p * Jn + j[n]] += s;", "E[p * Jn + j[0] % Jn] += s;"),
+    "E_includes_own_mode": ("if (k != n) s *= row_of", "if (k != n || 1) s *= row_of"),
+    "unfold_mode_order": ("for (int k = 0; k < N; k++) {\n        if (k == n) continue;",
+                          "for (int k = N - 1; k >= 0; k--) {\n        if (k == n) continue;"),
+    "feistel_three_rounds": ("for (int r = 0; r < 4; r++) {\n        uint64_t F = orc_sm64(R ^ key[r]) & mask;",
+                             "for (int r = 0; r < 3; r++) {\n        uint64_t F = orc_sm64(R ^ key[r]) & mask;"),
+    "segment_order_desc": ("return pa < pb ? -1 : (pa > pb ? 1 : 0);", "return pa < pb ? 1 : (pa > pb ? -1 : 0);"),
+    "modes_before_core": ("int rc = orc_core_step(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G);\n    for (int n = 0; rc == ORC_OK && n < N; n++)\n        rc = orc_mode_step(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A);",
+                          "int rc = ORC_OK;\n    for (int n = 0; rc == ORC_OK && n < N; n++)\n        rc = orc_mode_step(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A);\n    if (rc == ORC_OK) rc = orc_core_step(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G);"),
+    "ragged_batch_dropped": ("int64_t m = (T - b0 < M) ? (T - b0) : M;", "int64_t m = M; if (T - b0 < M) break;"),
+}
+
+
+def _pin_calls():
+    return [
+        (pins.test_perm_frozen_vectors, {}),
+        (pins.test_unfolding_columns_paper_example, {}),
+        (pins.test_segments_paper_example, {}),
+        (pins.test_predict_matches_dense_tucker, {"dims": (3, 4, 2, 3), "ranks": (2, 1, 2, 3)}),
+        (pins.test_unfolding_kronecker_identity, {"n": 1}),
+        (pins.test_core_step_is_gradient_of_fC, {"dims": (4, 3, 5), "ranks": (2, 3, 2)}),
+        (pins.test_mode_step_is_gradient_of_row_objective, {"n": 0}),
+        (pins.test_mode_step_is_gradient_of_row_objective, {"n": 2}),
+        (pins.test_step_order_core_then_modes, {}),
+        (pins.test_matrix_factorisation_exact, {}),
+        (pins.test_run_uses_sampler_and_ragged_last_batch, {}),
+    ]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(oracle_mod, tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found: " + name
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(old, new))
+    lib = tmp_path / ("lib_%s.so" % name)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", str(lib), str(mpath), "-lm"])
+    oracle_mod.use_library(str(lib))
+    failed = []
+    try:
+        for fn, kw in _pin_calls():
+            try:
+                fn(oracle_mod, **kw)
+            except (AssertionError, oracle_mod.OracleError, ValueError, IndexError):
+                failed.append(fn.__name__)
+    finally:
+        oracle_mod.use_library(None)
+    assert failed, "no pin caught mutant " + name
