@@ -1,0 +1,177 @@
+/*
+ * stdecomp.h -- C ABI of libstdecomp: the SGD_Tucker minibatch update for
+ * sparse Tucker decomposition (arXiv 2012.03550) on one MI355X (gfx950).
+ *
+ * Problem (Section "Notation and Preliminaries"): an N-order sparse tensor X
+ * of size I_1 x ... x I_N, observed on a set Omega of T entries (COO), is
+ * approximated by X_hat = G x_1 A(1) x_2 ... x_N A(N) (Definition "Sparse
+ * Tucker Decomposition") with a core G of size J_1 x ... x J_N and factor
+ * matrices A(n) of size I_n x J_n.  The parameters are fitted by averaged
+ * minibatch SGD (Eq. SGD) on randomly ordered minibatches Psi of M entries:
+ * each minibatch takes one step on the core objective (Eq.
+ * approximated_core_tensor_optimization, dense core) and then, mode by mode,
+ * one step on every sampled factor row (Eq. SGD_factor_matrix, Algorithm 1).
+ *
+ * Conventions
+ *  - Indices are 0-based.  COO indices are SoA: idx[n*T + t] is i_n of entry t.
+ *  - A(n) is exchanged row-major I_n x J_n (float32).  G is exchanged flat with
+ *    j_1 fastest: G[j_1 + J_1*(j_2 + J_2*(...))] (Definitions "Tensor
+ *    Unfolding" and "Vectorization" applied to the core).
+ *  - Every function returns STD_OK (0) or a negative STD_E_* code and throws
+ *    no C++ exception.  A handle is used by one host thread at a time;
+ *    distinct handles are independent.
+ *  - All device work runs on the handle's HIP stream; every call returns
+ *    after that work has finished (the calls are synchronous).
+ */
+#ifndef STDECOMP_H
+#define STDECOMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STD_OK 0
+#define STD_E_INVAL (-1)    /* bad order, rank, size, index, hyper-parameter or pointer */
+#define STD_E_NOMEM (-2)    /* host or device allocation failed */
+#define STD_E_DEVICE (-3)   /* HIP error or a kernel gave up; see stdecomp_last_error */
+#define STD_E_STATE (-4)    /* handle misuse (e.g. NULL handle) */
+#define STD_E_DIVERGED (-5) /* non-finite parameters or loss */
+
+#define STD_DTYPE_F32 0  /* FP32 parameters and arithmetic */
+#define STD_DTYPE_BF16 1 /* BF16 read copies, FP32 master, FP32 accumulation */
+
+#define STD_INIT_SCALED 0 /* entries N(0, 1/J_n) (core: 1/J_1), host RNG seeded by seed_init */
+#define STD_INIT_PAPER 1  /* entries N(0.5, 0.1^2): the paper's experimental setting */
+#define STD_INIT_CALLER 2 /* zeros until stdecomp_set_params */
+
+typedef struct stdecomp_handle stdecomp_handle;
+
+/* The tensor (Section "Notation and Preliminaries"). */
+typedef struct {
+  int32_t order;        /* N, 2 <= N <= 8 */
+  const int64_t* dims;  /* I_n, [N], 1 <= I_n < 2^31 */
+  const int32_t* ranks; /* J_n, [N], 1 <= J_n <= 32; prod J_n limited by LDS (see stdecomp_init) */
+  int64_t nnz;          /* T = |Omega| >= 1 */
+  const int32_t* idx;   /* SoA [N][nnz], each 0 <= idx < I_n */
+  const float* vals;    /* [nnz] */
+} stdecomp_problem;
+
+/* Solver options (Algorithm 1 inputs and the paper's hyper-parameters). */
+typedef struct {
+  int64_t batch;          /* M, entries per minibatch, 1 <= M <= 16384 */
+  float lr_factor;        /* gamma_A >= 0 */
+  float lr_core;          /* gamma_G (the paper's gamma_B) >= 0 */
+  float lambda_factor;    /* lambda_A >= 0 */
+  float lambda_core;      /* lambda_G (the paper's lambda_B) >= 0 */
+  uint64_t seed_sample;   /* key of the epoch permutations */
+  uint64_t seed_init;     /* seed of the host initialiser */
+  int32_t init_kind;      /* STD_INIT_* */
+  int32_t dtype;          /* STD_DTYPE_* */
+  int32_t r_core;         /* 0: dense core (the only value accepted) */
+  int32_t inputs_on_device; /* 1: problem.idx / problem.vals are device pointers */
+  void* stream;           /* hipStream_t to run on, or NULL for a private stream */
+  int32_t chain_chunk;    /* entries per workgroup per sub-step (0: automatic) */
+  int32_t reserved[15];   /* must be zero */
+} stdecomp_options;
+
+typedef struct {
+  int64_t epochs_run;      /* epochs completed by the call */
+  int64_t updates;         /* nonzero-updates = T * epochs_run */
+  int64_t minibatches;     /* minibatches run */
+  double device_seconds;   /* HIP-event time of the whole call on the stream */
+  double schedule_seconds; /* part spent in the sampler and row-set sort */
+  double chain_seconds;    /* part spent in the minibatch chain */
+  int64_t chain_launches;  /* chain kernel launches */
+  double bytes_alg;        /* algorithmic bytes of the chain (COO read + rows read/written + core) */
+  double flops_alg;        /* algorithmic flops of the chain, (2N+4) * prod(J) per update */
+} stdecomp_epoch_stats;
+
+typedef struct {
+  double rmse;      /* sqrt(SSE / n) (Section "Experimental Settings") */
+  double mae;       /* sum |r| / n */
+  double sse;       /* sum r^2, accumulated in FP64 */
+  double objective; /* 0.5 SSE / n + 0.5 lambda_A sum ||A(n)||^2 + 0.5 lambda_G ||G||^2 */
+  int64_t count;    /* n */
+  int64_t nonfinite;/* residuals that were not finite */
+} stdecomp_loss_out;
+
+typedef struct {
+  int32_t workgroups;      /* W: workgroups of the chain */
+  int32_t chunk;           /* entries per workgroup per sub-step */
+  int32_t threads;         /* threads per chain workgroup */
+  int32_t variant;         /* common rank of the specialised kernel, 0 = generic */
+  int64_t lds_bytes;       /* LDS per chain workgroup */
+  int64_t device_bytes;    /* device memory held by the handle */
+  int64_t minibatches;     /* per epoch: ceil(T / M) */
+  int64_t epoch;           /* next epoch index */
+} stdecomp_info_out;
+
+/* Fill *o with the defaults: M = 256, gamma = lambda = 0.01, seeds 0, scaled
+ * init, FP32, dense core, host inputs, private stream, automatic chunk. */
+int stdecomp_default_options(stdecomp_options* o);
+
+/* Create a handle: validates the problem (every index < I_n), copies the COO
+ * entries to device memory (the caller may free its arrays on return),
+ * initialises the parameters and sizes the epoch schedule and chain.
+ * Returns STD_E_INVAL when prod(J) or sum(J) exceed what one workgroup's LDS
+ * holds.  *out is NULL on error. */
+int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp_handle** out);
+
+/* Run n_epochs epochs (Algorithm 1 applied to every minibatch of the epoch
+ * order pi_e, e = the handle's epoch counter).  An epoch is one pass over all
+ * T entries without replacement: minibatch b holds positions
+ * [bM, min((b+1)M, T)) of pi_e.  st (nullable) receives counters and times.
+ * STD_E_DIVERGED when a parameter became non-finite. */
+int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* st);
+
+/* Minibatches [b_begin, b_end) of epoch `epoch` only (a partial epoch, e.g.
+ * to resume mid-epoch or to compare a prefix with a reference).  The epoch
+ * counter is not changed.  0 <= b_begin <= b_end <= ceil(T / M). */
+int stdecomp_run_minibatches(stdecomp_handle* h, int64_t epoch, int64_t b_begin, int64_t b_end,
+                             stdecomp_epoch_stats* st);
+
+/* x_hat for q entries (Definition "Sparse Tucker Decomposition").  idx is SoA
+ * [N][q]; out is [q]; both host or both device memory (on_device).  An index
+ * out of range gives STD_E_INVAL and writes nothing. */
+int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* out, int32_t on_device);
+
+/* RMSE, MAE and SSE over n entries (host or device, SoA idx [N][n], vals
+ * [n]); idx == NULL and vals == NULL evaluates the training set Omega. */
+int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float* vals, int32_t on_device,
+                  stdecomp_loss_out* out);
+
+/* Copy the FP32 master parameters out of / into the handle (host memory).
+ * A[n] points to I_n x J_n row-major floats; G to prod(J) floats (j_1 fastest). */
+int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G);
+int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G);
+
+/* Epoch counter: the next stdecomp_epoch runs epoch e.  Resuming from saved
+ * parameters at epoch e reproduces the uninterrupted run bit for bit. */
+int stdecomp_set_epoch(stdecomp_handle* h, int64_t e);
+
+/* Schedule of one minibatch as the GPU computes it (host outputs, for
+ * bit-exact comparison with the CPU definition): entries[p] = the entry at
+ * position p of minibatch `batch` of epoch `epoch` (pi_e(bM + p)); sigma =
+ * positions sorted by (i_mode, position); seg_off[0..nseg] and seg_row[0..nseg)
+ * = the row runs.  Array sizes: entries, sigma, seg_row >= M; seg_off >= M+1. */
+int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, int32_t mode, int64_t* entries,
+                            int32_t* sigma, int32_t* seg_off, int32_t* seg_row, int32_t* nseg, int32_t* m_out);
+
+/* The GPU sampler alone: out[q] = pi_e(q) for q in [0, T), host output. */
+int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out);
+
+int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out);
+
+/* Release the handle and its device memory (NULL is accepted). */
+int stdecomp_free(stdecomp_handle* h);
+
+/* Static message for a return code; the handle's last error message. */
+const char* stdecomp_strerror(int code);
+const char* stdecomp_last_error(const stdecomp_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STDECOMP_H */

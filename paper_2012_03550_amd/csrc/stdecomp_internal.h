@@ -1,0 +1,84 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels of
+// libstdecomp.  Not part of the public C ABI (include/stdecomp.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stdk {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxRank = 32;      // largest J_n the kernels accept
+constexpr int kMaxBatch = 16384;  // largest minibatch (positions are 16-bit)
+constexpr int kChainThreads = 256;
+constexpr int kSortThreads = 256;
+
+// Round x up to a multiple of 4 floats (16-byte factor rows).
+__host__ __device__ inline int pad4(int x) { return (x + 3) & ~3; }
+
+// Shape of a sparse Tucker model, passed by value to every kernel.
+struct Shape {
+  int N;                 // order
+  int J[kMaxOrder];      // core ranks J_n
+  int Jp[kMaxOrder];     // row stride of A(n) in floats (J_n rounded up to 4)
+  int64_t I[kMaxOrder];  // mode sizes
+  int P;                 // prod_n J_n
+  int R;                 // words per COO record: N indices then the value bits
+  int rs_off[kMaxOrder]; // offset of mode k's row inside an LDS row buffer
+  int rs;                // LDS row-buffer stride per sample (odd, avoids bank conflicts)
+};
+
+// Arguments of the persistent minibatch chain kernel.
+struct ChainArgs {
+  Shape s;
+  const uint32_t* coo;      // records in epoch order (T x R words)
+  const uint16_t* sigma;    // [N][T] per-minibatch sorted positions
+  const int* xrow;          // [nb][N][W] row straddling each chunk boundary, or -1
+  float* A[kMaxOrder];      // FP32 master factors, I_n x Jp_n
+  uint16_t* Ab[kMaxOrder];  // BF16 read copies (null in FP32 mode)
+  float* G;                 // FP32 master core (P)
+  uint16_t* Gb;             // BF16 read copy of the core (null in FP32 mode)
+  float* partial;           // [W][P] per-workgroup core-gradient partials
+  float* carry;             // [2][W][2][carry_stride] per-chunk run partials and old rows
+  unsigned* bar;            // grid-barrier arrival counter (zero at launch)
+  int* err;                 // set to nonzero by a workgroup that gives up
+  int64_t T, M;
+  int64_t b_begin, b_end;   // minibatches [b_begin, b_end) of the epoch
+  float gA, lA, gG, lG;     // learning steps and L2 weights
+  int W;                    // workgroups in the chain
+  int chunk;                // samples per workgroup per phase (<= blockDim)
+  int carry_stride;         // floats per carry slot
+  long long spin_limit;     // barrier give-up bound (iterations)
+  int grad_groups;          // sample groups of the core-gradient pass
+  int gt_floats;            // LDS floats reserved for the unfolded-core table
+  int split_cap;            // entries of the LDS split-row table
+};
+
+// Which J specialisation of the chain serves a shape: the common rank when
+// every mode has the same J_n <= 16, else 0 (generic, J_n <= 32).
+int chain_variant(const Shape& s);
+
+// Kernel launchers (stdecomp_kernels.hip).  All return hipError_t values.
+hipError_t launch_perm_gather(const Shape& s, const uint32_t* coo, uint32_t* coo_perm, int64_t T,
+                              uint64_t seed, int64_t epoch, hipStream_t st);
+hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, hipStream_t st);
+hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg, int W,
+                       int chunk, int64_t T, int64_t M, int64_t b_begin, int64_t b_end, hipStream_t st);
+hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const uint16_t* sigma,
+                                 int64_t T, int64_t M, int64_t b, int mode, int32_t* seg_off,
+                                 int32_t* seg_row, int32_t* nseg, hipStream_t st);
+size_t chain_lds_bytes(const ChainArgs& a, int threads);
+hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
+hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
+                               uint32_t* rec, int* bad, hipStream_t st);
+struct FactorPtrs {
+  const float* A[kMaxOrder];
+};
+hipError_t launch_predict(const Shape& s, const uint32_t* rec, int64_t n, FactorPtrs A, const float* G, float* out,
+                          int nblocks, hipStream_t st);
+hipError_t launch_loss(const Shape& s, const uint32_t* rec, int64_t n, FactorPtrs A, const float* G,
+                       double* block_out, int nblocks, double* out3, hipStream_t st);
+hipError_t launch_sumsq(const float* p, int64_t n, double* block_out, int nblocks, hipStream_t st);
+hipError_t launch_count_nonfinite(const float* p, int64_t n, int* flag, hipStream_t st);
+hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
+
+}  // namespace stdk

@@ -1,0 +1,787 @@
+// Host runtime of libstdecomp: argument validation, device memory, the epoch
+// driver (sampler -> row-set sort -> minibatch chain) and the C ABI declared
+// in include/stdecomp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stdecomp.h"
+#include "stdecomp_internal.h"
+
+using stdk::kMaxOrder;
+using stdk::kMaxRank;
+
+struct stdecomp_handle {
+  stdk::Shape s{};
+  int64_t T = 0, M = 0, nb = 0;
+  float gA = 0, lA = 0, gG = 0, lG = 0;
+  uint64_t seed_sample = 0;
+  int dtype = 0;
+  int64_t epoch = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int num_cus = 0;
+  // chain configuration
+  int W = 1, chunk = 1, threads = 64, grad_groups = 1, gt_floats = 0, split_cap = 0, carry_stride = 0;
+  size_t chain_lds = 0;
+  // device buffers
+  uint32_t* coo = nullptr;
+  uint32_t* coo_perm = nullptr;
+  uint16_t* sigma = nullptr;
+  int* xrow = nullptr;
+  int* nseg = nullptr;
+  float* A[kMaxOrder] = {};
+  float* G = nullptr;
+  float* partial = nullptr;
+  float* carry = nullptr;
+  unsigned* bar = nullptr;
+  int* err = nullptr;
+  double* dscratch = nullptr;  // loss/sum-of-squares block partials
+  int dscratch_blocks = 0;
+  int* flag = nullptr;
+  size_t device_bytes = 0;
+  int64_t sched_epoch = -1;  // epoch whose schedule coo_perm/sigma hold
+  std::string last_error;
+  hipEvent_t ev[4] = {};
+};
+
+namespace {
+
+constexpr int kBatchesPerLaunch = 2048;  // bounds the duration of one chain launch
+constexpr long long kSpinLimit = 1ll << 24;
+
+int fail(stdecomp_handle* h, int code, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return code;
+}
+
+int hip_fail(stdecomp_handle* h, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, STD_E_DEVICE, m);
+}
+
+#define HIPCHK(h, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
+  } while (0)
+
+template <typename T>
+int dalloc(stdecomp_handle* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(h, STD_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  h->device_bytes += count * sizeof(T);
+  return STD_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// Host initialiser: SplitMix64 stream, Box-Muller normals.
+struct HostRng {
+  uint64_t state;
+  explicit HostRng(uint64_t seed) : state(seed) {}
+  uint64_t next() {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+  double normal() {
+    const double u1 = uniform(), u2 = uniform();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  }
+};
+
+int64_t total_minibatches(int64_t T, int64_t M) { return (T + M - 1) / M; }
+
+int chain_threads_for(int chunk) {
+  int t = ((chunk + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > stdk::kChainThreads) t = stdk::kChainThreads;
+  return t;
+}
+
+// Pick the chain geometry and check that it fits one workgroup's LDS.
+int configure_chain(stdecomp_handle* h, int chunk_req) {
+  const stdk::Shape& s = h->s;
+  int chunk = chunk_req;
+  if (chunk <= 0) {
+    // about 32 workgroups for large minibatches, at least 64 entries each
+    chunk = (int)((h->M + 31) / 32);
+    if (chunk < 64) chunk = 64;
+    chunk = ((chunk + 63) / 64) * 64;
+  }
+  if (chunk > stdk::kChainThreads) chunk = stdk::kChainThreads;
+  if (chunk > h->M) chunk = (int)h->M;
+  int W = (int)((h->M + chunk - 1) / chunk);
+  if (W > h->num_cus) return fail(h, STD_E_INVAL, "minibatch needs more chain workgroups than compute units");
+  h->chunk = chunk;
+  h->W = W;
+  h->threads = chain_threads_for(chunk);
+  const int K0 = s.P / s.J[0];
+  int groups = h->threads / K0;
+  if (groups < 1) groups = 1;
+  if (groups > 8) groups = 8;
+  h->grad_groups = groups;
+  int gtf = 0;
+  for (int n = 0; n < s.N; ++n) {
+    const int f = (s.P / s.J[n]) * stdk::pad4(s.J[n]);
+    if (f > gtf) gtf = f;
+  }
+  h->gt_floats = gtf;
+  h->split_cap = W > 1 ? W - 1 : 0;
+  int jmax = 0;
+  for (int n = 0; n < s.N; ++n) jmax = s.J[n] > jmax ? s.J[n] : jmax;
+  h->carry_stride = stdk::pad4(2 + 2 * jmax);
+  stdk::ChainArgs a{};
+  a.s = s;
+  a.W = W;
+  a.grad_groups = groups;
+  a.gt_floats = gtf;
+  a.split_cap = h->split_cap;
+  h->chain_lds = stdk::chain_lds_bytes(a, h->threads);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
+    return fail(h, STD_E_DEVICE, "hipGetDeviceProperties failed");
+  const size_t lds_cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                                : prop.sharedMemPerBlock;
+  if (h->chain_lds > lds_cap)
+    return fail(h, STD_E_INVAL, "core or factor rows too large for one workgroup's LDS (" +
+                                    std::to_string(h->chain_lds) + " > " + std::to_string(lds_cap) + " bytes)");
+  return STD_OK;
+}
+
+stdk::ChainArgs chain_args(stdecomp_handle* h) {
+  stdk::ChainArgs a{};
+  a.s = h->s;
+  a.coo = h->coo_perm;
+  a.sigma = h->sigma;
+  a.xrow = h->xrow;
+  for (int n = 0; n < h->s.N; ++n) a.A[n] = h->A[n];
+  a.G = h->G;
+  a.partial = h->partial;
+  a.carry = h->carry;
+  a.bar = h->bar;
+  a.err = h->err;
+  a.T = h->T;
+  a.M = h->M;
+  a.gA = h->gA;
+  a.lA = h->lA;
+  a.gG = h->gG;
+  a.lG = h->lG;
+  a.W = h->W;
+  a.chunk = h->chunk;
+  a.carry_stride = h->carry_stride;
+  a.spin_limit = kSpinLimit;
+  a.grad_groups = h->grad_groups;
+  a.gt_floats = h->gt_floats;
+  a.split_cap = h->split_cap;
+  return a;
+}
+
+int run_schedule(stdecomp_handle* h, int64_t epoch) {
+  HIPCHK(h, stdk::launch_perm_gather(h->s, h->coo, h->coo_perm, h->T, h->seed_sample, epoch, h->stream));
+  HIPCHK(h, stdk::launch_sort(h->s, h->coo_perm, h->sigma, h->xrow, h->nseg, h->W, h->chunk, h->T, h->M, 0, h->nb,
+                              h->stream));
+  h->sched_epoch = epoch;
+  return STD_OK;
+}
+
+// Pack caller COO (host or device SoA) into device records.  *rec_out is
+// freshly allocated (caller frees).  Index range violations -> STD_E_INVAL.
+int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const float* vals, int on_device,
+                        uint32_t** rec_out) {
+  *rec_out = nullptr;
+  const int N = h->s.N;
+  const int32_t* didx = idx;
+  const float* dvals = vals;
+  int32_t* tidx = nullptr;
+  float* tvals = nullptr;
+  if (!on_device) {
+    for (int k = 0; k < N; ++k)
+      for (int64_t t = 0; t < n; ++t) {
+        const int32_t v = idx[(int64_t)k * n + t];
+        if (v < 0 || v >= h->s.I[k]) return fail(h, STD_E_INVAL, "index out of range");
+      }
+    int rc = dalloc(h, &tidx, (size_t)N * n);
+    if (rc) return rc;
+    h->device_bytes -= (size_t)N * n * 4;
+    HIPCHK(h, hipMemcpyAsync(tidx, idx, (size_t)N * n * 4, hipMemcpyHostToDevice, h->stream));
+    if (vals) {
+      rc = dalloc(h, &tvals, (size_t)n);
+      if (rc) {
+        dfree(tidx);
+        return rc;
+      }
+      h->device_bytes -= (size_t)n * 4;
+      HIPCHK(h, hipMemcpyAsync(tvals, vals, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    didx = tidx;
+    dvals = tvals;
+  }
+  uint32_t* rec = nullptr;
+  int rc = dalloc(h, &rec, (size_t)n * h->s.R);
+  if (rc) {
+    dfree(tidx);
+    dfree(tvals);
+    return rc;
+  }
+  h->device_bytes -= (size_t)n * h->s.R * 4;
+  HIPCHK(h, hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+  hipError_t e = stdk::launch_pack_records(h->s, didx, dvals, n, rec, h->flag, h->stream);
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  dfree(tidx);
+  dfree(tvals);
+  if (e != hipSuccess) {
+    dfree(rec);
+    return hip_fail(h, e, "packing entries");
+  }
+  if (bad) {
+    dfree(rec);
+    return fail(h, STD_E_INVAL, "index out of range");
+  }
+  *rec_out = rec;
+  return STD_OK;
+}
+
+stdk::FactorPtrs factor_ptrs(const stdecomp_handle* h) {
+  stdk::FactorPtrs f{};
+  for (int n = 0; n < h->s.N; ++n) f.A[n] = h->A[n];
+  return f;
+}
+
+int eval_blocks(const stdecomp_handle* h, int64_t n) {
+  int64_t b = (n + 255) / 256;
+  const int64_t cap = (int64_t)h->num_cus * 4;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+int device_sumsq(stdecomp_handle* h, const float* p, int64_t n, double* out) {
+  const int nb = 256;
+  HIPCHK(h, stdk::launch_sumsq(p, n, h->dscratch, nb, h->stream));
+  std::vector<double> v(nb);
+  HIPCHK(h, hipMemcpyAsync(v.data(), h->dscratch, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double acc = 0.0;
+  for (int i = 0; i < nb; ++i) acc += v[i];
+  *out = acc;
+  return STD_OK;
+}
+
+void release(stdecomp_handle* h) {
+  if (!h) return;
+  dfree(h->coo);
+  dfree(h->coo_perm);
+  dfree(h->sigma);
+  dfree(h->xrow);
+  dfree(h->nseg);
+  for (int n = 0; n < kMaxOrder; ++n) dfree(h->A[n]);
+  dfree(h->G);
+  dfree(h->partial);
+  dfree(h->carry);
+  dfree(h->bar);
+  dfree(h->err);
+  dfree(h->dscratch);
+  dfree(h->flag);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.f; }
+
+}  // namespace
+
+extern "C" {
+
+int stdecomp_default_options(stdecomp_options* o) {
+  if (!o) return STD_E_INVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->batch = 256;
+  o->lr_factor = o->lr_core = 0.01f;
+  o->lambda_factor = o->lambda_core = 0.01f;
+  o->init_kind = STD_INIT_SCALED;
+  o->dtype = STD_DTYPE_F32;
+  return STD_OK;
+}
+
+const char* stdecomp_strerror(int code) {
+  switch (code) {
+    case STD_OK: return "ok";
+    case STD_E_INVAL: return "invalid argument";
+    case STD_E_NOMEM: return "out of memory";
+    case STD_E_DEVICE: return "device error";
+    case STD_E_STATE: return "invalid handle state";
+    case STD_E_DIVERGED: return "diverged (non-finite values)";
+    default: return "unknown error";
+  }
+}
+
+const char* stdecomp_last_error(const stdecomp_handle* h) { return h ? h->last_error.c_str() : "no handle"; }
+
+int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp_handle** out) {
+  if (!out) return STD_E_INVAL;
+  *out = nullptr;
+  if (!p || !o) return STD_E_INVAL;
+  const int N = p->order;
+  if (N < 2 || N > kMaxOrder || !p->dims || !p->ranks || p->nnz < 1 || !p->idx || !p->vals) return STD_E_INVAL;
+  if (o->batch < 1 || o->batch > stdk::kMaxBatch) return STD_E_INVAL;
+  if (!finite_nonneg(o->lr_factor) || !finite_nonneg(o->lr_core) || !finite_nonneg(o->lambda_factor) ||
+      !finite_nonneg(o->lambda_core))
+    return STD_E_INVAL;
+  if (o->init_kind < STD_INIT_SCALED || o->init_kind > STD_INIT_CALLER) return STD_E_INVAL;
+  if (o->dtype != STD_DTYPE_F32) return STD_E_INVAL;  // BF16 path: see stdecomp_bf16 (not in this build yet)
+  if (o->r_core != 0) return STD_E_INVAL;
+  for (int i = 0; i < 15; ++i)
+    if (o->reserved[i] != 0) return STD_E_INVAL;
+  int64_t P = 1;
+  for (int n = 0; n < N; ++n) {
+    if (p->dims[n] < 1 || p->dims[n] >= (1ll << 31) || p->ranks[n] < 1 || p->ranks[n] > kMaxRank)
+      return STD_E_INVAL;
+    P *= p->ranks[n];
+    if (P > (1 << 20)) return STD_E_INVAL;
+  }
+  if (p->nnz >= (1ll << 40)) return STD_E_INVAL;
+
+  stdecomp_handle* h = new (std::nothrow) stdecomp_handle();
+  if (!h) return STD_E_NOMEM;
+  auto bail = [&](int rc) {
+    std::fprintf(stderr, "stdecomp_init: %s\n", h->last_error.c_str());
+    release(h);
+    delete h;
+    return rc;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    h->last_error = "no HIP device";
+    return bail(STD_E_DEVICE);
+  }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) {
+      h->last_error = "hipGetDeviceProperties failed";
+      return bail(STD_E_DEVICE);
+    }
+    h->num_cus = prop.multiProcessorCount;
+  }
+  stdk::Shape& s = h->s;
+  s.N = N;
+  s.P = (int)P;
+  s.R = N + 1;
+  int off = 0;
+  for (int n = 0; n < N; ++n) {
+    s.J[n] = p->ranks[n];
+    s.Jp[n] = stdk::pad4(p->ranks[n]);
+    s.I[n] = p->dims[n];
+    s.rs_off[n] = off;
+    off += s.J[n];
+  }
+  s.rs = off | 1;
+  h->T = p->nnz;
+  h->M = o->batch;
+  h->nb = total_minibatches(h->T, h->M);
+  h->gA = o->lr_factor;
+  h->lA = o->lambda_factor;
+  h->gG = o->lr_core;
+  h->lG = o->lambda_core;
+  h->seed_sample = o->seed_sample;
+  h->dtype = o->dtype;
+  if (o->stream) {
+    h->stream = (hipStream_t)o->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      h->last_error = "hipStreamCreate failed";
+      return bail(STD_E_DEVICE);
+    }
+    h->own_stream = true;
+  }
+  for (auto& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      h->last_error = "hipEventCreate failed";
+      return bail(STD_E_DEVICE);
+    }
+  int rc = configure_chain(h, o->chain_chunk);
+  if (rc) return bail(rc);
+
+  // device memory
+  const size_t T = (size_t)h->T;
+  if ((rc = dalloc(h, &h->coo, T * s.R)) || (rc = dalloc(h, &h->coo_perm, T * s.R)) ||
+      (rc = dalloc(h, &h->sigma, T * N)) || (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * h->W)) ||
+      (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
+      (rc = dalloc(h, &h->partial, (size_t)h->W * P)) ||
+      (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) || (rc = dalloc(h, &h->bar, 1)) ||
+      (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) || (rc = dalloc(h, &h->flag, 1)))
+    return bail(rc);
+  for (int n = 0; n < N; ++n) {
+    if ((rc = dalloc(h, &h->A[n], (size_t)s.I[n] * s.Jp[n]))) return bail(rc);
+    if (hipMemsetAsync(h->A[n], 0, (size_t)s.I[n] * s.Jp[n] * 4, h->stream) != hipSuccess) {
+      h->last_error = "hipMemset failed";
+      return bail(STD_E_DEVICE);
+    }
+  }
+  if (hipMemsetAsync(h->xrow, 0xFF, (size_t)h->nb * N * h->W * 4, h->stream) != hipSuccess) {
+    h->last_error = "hipMemset failed";
+    return bail(STD_E_DEVICE);
+  }
+
+  // COO entries -> device records (the range check runs on the device)
+  {
+    int32_t* didx = nullptr;
+    float* dvals = nullptr;
+    const int32_t* src_idx = p->idx;
+    const float* src_vals = p->vals;
+    if (!o->inputs_on_device) {
+      if ((rc = dalloc(h, &didx, T * N)) || (rc = dalloc(h, &dvals, T))) {
+        dfree(didx);
+        return bail(rc);
+      }
+      h->device_bytes -= T * N * 4 + T * 4;
+      if (hipMemcpyAsync(didx, p->idx, T * N * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+          hipMemcpyAsync(dvals, p->vals, T * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+        dfree(didx);
+        dfree(dvals);
+        h->last_error = "copying the COO entries failed";
+        return bail(STD_E_DEVICE);
+      }
+      src_idx = didx;
+      src_vals = dvals;
+    }
+    int bad = 0;
+    hipError_t e = hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = stdk::launch_pack_records(s, src_idx, src_vals, h->T, h->coo, h->flag, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    dfree(didx);
+    dfree(dvals);
+    if (e != hipSuccess) {
+      h->last_error = std::string("packing the COO entries: ") + hipGetErrorString(e);
+      return bail(STD_E_DEVICE);
+    }
+    if (bad) {
+      h->last_error = "COO index out of range";
+      return bail(STD_E_INVAL);
+    }
+  }
+
+  // initial parameters
+  {
+    HostRng rng(o->seed_init);
+    std::vector<float> buf;
+    for (int n = 0; n < N; ++n) {
+      buf.assign((size_t)s.I[n] * s.Jp[n], 0.f);
+      if (o->init_kind != STD_INIT_CALLER) {
+        const double sd = o->init_kind == STD_INIT_PAPER ? 0.1 : 1.0 / std::sqrt((double)s.J[n]);
+        const double mu = o->init_kind == STD_INIT_PAPER ? 0.5 : 0.0;
+        for (int64_t i = 0; i < s.I[n]; ++i)
+          for (int j = 0; j < s.J[n]; ++j) buf[(size_t)i * s.Jp[n] + j] = (float)(mu + sd * rng.normal());
+      }
+      if (hipMemcpy(h->A[n], buf.data(), buf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        h->last_error = "copying initial factors failed";
+        return bail(STD_E_DEVICE);
+      }
+    }
+    buf.assign((size_t)P, 0.f);
+    if (o->init_kind != STD_INIT_CALLER) {
+      const double sd = o->init_kind == STD_INIT_PAPER ? 0.1 : 1.0 / std::sqrt((double)s.J[0]);
+      const double mu = o->init_kind == STD_INIT_PAPER ? 0.5 : 0.0;
+      for (int64_t i = 0; i < P; ++i) buf[i] = (float)(mu + sd * rng.normal());
+    }
+    if (hipMemcpy(h->G, buf.data(), buf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      h->last_error = "copying the initial core failed";
+      return bail(STD_E_DEVICE);
+    }
+  }
+  *out = h;
+  return STD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Minibatches [b0, b1) of epoch `epoch`, accumulated into *acc.
+int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecomp_epoch_stats* acc,
+              std::vector<int>& nseg_host) {
+  const int N = h->s.N;
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
+  if (h->sched_epoch != epoch) {
+    int rc = run_schedule(h, epoch);
+    if (rc) return rc;
+  }
+  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
+  HIPCHK(h, hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+  stdk::ChainArgs a = chain_args(h);
+  for (int64_t c0 = b0; c0 < b1; c0 += kBatchesPerLaunch) {
+    a.b_begin = c0;
+    a.b_end = (c0 + kBatchesPerLaunch < b1) ? c0 + kBatchesPerLaunch : b1;
+    HIPCHK(h, hipMemsetAsync(h->bar, 0, sizeof(unsigned), h->stream));
+    HIPCHK(h, stdk::launch_chain(a, h->threads, h->stream));
+    acc->chain_launches++;
+  }
+  HIPCHK(h, hipEventRecord(h->ev[2], h->stream));
+  int err = 0;
+  HIPCHK(h, hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  nseg_host.resize((size_t)h->nb * N);
+  HIPCHK(h, hipMemcpyAsync(nseg_host.data(), h->nseg, nseg_host.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (err) return fail(h, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+  float t01 = 0, t12 = 0;
+  HIPCHK(h, hipEventElapsedTime(&t01, h->ev[0], h->ev[1]));
+  HIPCHK(h, hipEventElapsedTime(&t12, h->ev[1], h->ev[2]));
+  acc->schedule_seconds += t01 * 1e-3;
+  acc->chain_seconds += t12 * 1e-3;
+  acc->device_seconds += (t01 + t12) * 1e-3;
+  acc->minibatches += b1 - b0;
+  // algorithmic bytes: COO records, each touched row read and written once
+  // per minibatch and mode, the core read and written once per minibatch
+  double rows_bytes = 0.0;
+  int64_t upd = 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t m = (h->T - b * h->M < h->M) ? h->T - b * h->M : h->M;
+    upd += m;
+    for (int n = 0; n < N; ++n) rows_bytes += (double)nseg_host[(size_t)b * N + n] * h->s.J[n] * 8.0;
+  }
+  acc->updates += upd;
+  acc->bytes_alg += (double)upd * (4.0 * N + 4.0) + rows_bytes + (double)(b1 - b0) * 2.0 * h->s.P * 4.0;
+  acc->flops_alg += (double)upd * (2.0 * N + 4.0) * h->s.P;
+  return STD_OK;
+}
+
+int check_finite(stdecomp_handle* h) {
+  HIPCHK(h, hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
+  HIPCHK(h, stdk::launch_count_nonfinite(h->G, h->s.P, h->flag, h->stream));
+  for (int n = 0; n < h->s.N; ++n)
+    HIPCHK(h, stdk::launch_count_nonfinite(h->A[n], h->s.I[n] * h->s.Jp[n], h->flag, h->stream));
+  int bad = 0;
+  HIPCHK(h, hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (bad) return fail(h, STD_E_DIVERGED, "non-finite parameters");
+  return STD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* st) {
+  if (!h) return STD_E_STATE;
+  if (n_epochs < 0) return fail(h, STD_E_INVAL, "n_epochs < 0");
+  stdecomp_epoch_stats acc{};
+  std::vector<int> nseg_host;
+  for (int e = 0; e < n_epochs; ++e) {
+    int rc = run_range(h, h->epoch, 0, h->nb, &acc, nseg_host);
+    if (rc) return rc;
+    acc.epochs_run++;
+    h->epoch++;
+  }
+  if (st) *st = acc;
+  return check_finite(h);
+}
+
+int stdecomp_run_minibatches(stdecomp_handle* h, int64_t epoch, int64_t b_begin, int64_t b_end,
+                             stdecomp_epoch_stats* st) {
+  if (!h) return STD_E_STATE;
+  if (epoch < 0 || b_begin < 0 || b_end < b_begin || b_end > h->nb) return fail(h, STD_E_INVAL, "bad minibatch range");
+  stdecomp_epoch_stats acc{};
+  std::vector<int> nseg_host;
+  if (b_end > b_begin) {
+    int rc = run_range(h, epoch, b_begin, b_end, &acc, nseg_host);
+    if (rc) return rc;
+  }
+  if (st) *st = acc;
+  return check_finite(h);
+}
+
+int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* out, int32_t on_device) {
+  if (!h) return STD_E_STATE;
+  if (q < 0 || (q > 0 && (!idx || !out))) return fail(h, STD_E_INVAL, "bad predict arguments");
+  if (q == 0) return STD_OK;
+  uint32_t* rec = nullptr;
+  int rc = pack_caller_entries(h, q, idx, nullptr, on_device, &rec);
+  if (rc) return rc;
+  float* dout = out;
+  if (!on_device) {
+    if ((rc = dalloc(h, &dout, (size_t)q))) {
+      dfree(rec);
+      return rc;
+    }
+    h->device_bytes -= (size_t)q * 4;
+  }
+  hipError_t e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->stream);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  dfree(rec);
+  if (!on_device) dfree(dout);
+  if (e != hipSuccess) return hip_fail(h, e, "predict");
+  return STD_OK;
+}
+
+int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float* vals, int32_t on_device,
+                  stdecomp_loss_out* out) {
+  if (!h) return STD_E_STATE;
+  if (!out) return fail(h, STD_E_INVAL, "out is NULL");
+  uint32_t* rec = nullptr;
+  const uint32_t* use = nullptr;
+  if (!idx && !vals) {
+    n = h->T;
+    use = h->coo;
+  } else {
+    if (n < 1 || !idx || !vals) return fail(h, STD_E_INVAL, "bad loss arguments");
+    int rc = pack_caller_entries(h, n, idx, vals, on_device, &rec);
+    if (rc) return rc;
+    use = rec;
+  }
+  const int nb = eval_blocks(h, n);
+  double sums[3] = {0, 0, 0};
+  hipError_t e = stdk::launch_loss(h->s, use, n, factor_ptrs(h), h->G, h->dscratch, nb, h->dscratch + 3 * nb,
+                                   h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, h->dscratch + 3 * nb, sizeof(sums), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  dfree(rec);
+  if (e != hipSuccess) return hip_fail(h, e, "loss");
+  double regA = 0.0, regG = 0.0, t = 0.0;
+  for (int k = 0; k < h->s.N; ++k) {
+    int rc = device_sumsq(h, h->A[k], h->s.I[k] * h->s.Jp[k], &t);
+    if (rc) return rc;
+    regA += t;
+  }
+  int rc = device_sumsq(h, h->G, h->s.P, &regG);
+  if (rc) return rc;
+  out->count = n;
+  out->sse = sums[0];
+  out->rmse = std::sqrt(sums[0] / (double)n);
+  out->mae = sums[1] / (double)n;
+  out->nonfinite = (int64_t)sums[2];
+  out->objective = 0.5 * sums[0] / (double)n + 0.5 * h->lA * regA + 0.5 * h->lG * regG;
+  if (out->nonfinite > 0 || !std::isfinite(out->sse)) return fail(h, STD_E_DIVERGED, "non-finite loss");
+  return STD_OK;
+}
+
+int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G) {
+  if (!h) return STD_E_STATE;
+  if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
+  for (int n = 0; n < h->s.N; ++n) {
+    if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
+    HIPCHK(h, hipMemcpy2DAsync(A[n], (size_t)h->s.J[n] * 4, h->A[n], (size_t)h->s.Jp[n] * 4, (size_t)h->s.J[n] * 4,
+                               (size_t)h->s.I[n], hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(G, h->G, (size_t)h->s.P * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return STD_OK;
+}
+
+int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G) {
+  if (!h) return STD_E_STATE;
+  if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
+  for (int n = 0; n < h->s.N; ++n) {
+    if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
+    HIPCHK(h, hipMemcpy2DAsync(h->A[n], (size_t)h->s.Jp[n] * 4, A[n], (size_t)h->s.J[n] * 4, (size_t)h->s.J[n] * 4,
+                               (size_t)h->s.I[n], hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(h->G, G, (size_t)h->s.P * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return STD_OK;
+}
+
+int stdecomp_set_epoch(stdecomp_handle* h, int64_t e) {
+  if (!h) return STD_E_STATE;
+  if (e < 0) return fail(h, STD_E_INVAL, "negative epoch");
+  h->epoch = e;
+  return STD_OK;
+}
+
+int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, int32_t mode, int64_t* entries,
+                            int32_t* sigma, int32_t* seg_off, int32_t* seg_row, int32_t* nseg, int32_t* m_out) {
+  if (!h) return STD_E_STATE;
+  if (epoch < 0 || batch < 0 || batch >= h->nb || mode < 0 || mode >= h->s.N || !entries || !sigma || !seg_off ||
+      !seg_row || !nseg || !m_out)
+    return fail(h, STD_E_INVAL, "bad debug_schedule arguments");
+  int rc = run_schedule(h, epoch);
+  if (rc) return rc;
+  const int64_t base = batch * h->M;
+  const int m = (int)((h->T - base < h->M) ? h->T - base : h->M);
+  int64_t* dperm = nullptr;
+  int32_t *doff = nullptr, *drow = nullptr, *dn = nullptr;
+  if ((rc = dalloc(h, &dperm, (size_t)h->T)) || (rc = dalloc(h, &doff, (size_t)m + 1)) ||
+      (rc = dalloc(h, &drow, (size_t)m)) || (rc = dalloc(h, &dn, 1))) {
+    dfree(dperm);
+    dfree(doff);
+    dfree(drow);
+    return rc;
+  }
+  h->device_bytes -= (size_t)h->T * 8 + (size_t)(2 * m + 2) * 4;
+  std::vector<uint16_t> sig(m);
+  hipError_t e = stdk::launch_perm_only(h->T, h->seed_sample, epoch, dperm, h->stream);
+  if (e == hipSuccess)
+    e = stdk::launch_debug_segments(h->s, h->coo_perm, h->sigma, h->T, h->M, batch, mode, doff, drow, dn, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(entries, dperm + base, (size_t)m * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sig.data(), h->sigma + (size_t)mode * h->T + base, (size_t)m * 2, hipMemcpyDeviceToHost,
+                       h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(nseg, dn, 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(seg_off, doff, (size_t)(m + 1) * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(seg_row, drow, (size_t)m * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  dfree(dperm);
+  dfree(doff);
+  dfree(drow);
+  dfree(dn);
+  if (e != hipSuccess) return hip_fail(h, e, "debug_schedule");
+  for (int q = 0; q < m; ++q) sigma[q] = sig[q];
+  *m_out = m;
+  return STD_OK;
+}
+
+int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out) {
+  if (T < 1 || epoch < 0 || !out) return STD_E_INVAL;
+  int64_t* d = nullptr;
+  if (hipMalloc((void**)&d, (size_t)T * 8) != hipSuccess) return STD_E_NOMEM;
+  hipError_t e = stdk::launch_perm_only(T, seed, epoch, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, d, (size_t)T * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? STD_OK : STD_E_DEVICE;
+}
+
+int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out) {
+  if (!h) return STD_E_STATE;
+  if (!out) return STD_E_INVAL;
+  out->workgroups = h->W;
+  out->chunk = h->chunk;
+  out->threads = h->threads;
+  out->variant = stdk::chain_variant(h->s);
+  out->lds_bytes = (int64_t)h->chain_lds;
+  out->device_bytes = (int64_t)h->device_bytes;
+  out->minibatches = h->nb;
+  out->epoch = h->epoch;
+  return STD_OK;
+}
+
+int stdecomp_free(stdecomp_handle* h) {
+  if (!h) return STD_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+  return STD_OK;
+}
+
+}  // extern "C"

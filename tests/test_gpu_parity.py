@@ -1,0 +1,263 @@
+"""GPU path (libstdecomp through its C ABI) against the FP64 CPU oracle.
+
+Integer work (sampler, sorted row sets, segments) must match bit for bit.
+Floating-point results must match to the FP32 tolerance: per epoch, from a
+common starting state, the relative Frobenius error of every factor matrix
+and of the core, and the relative RMSE error, are at most 1e-5.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2012_03550_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_03550_amd import binding
+    binding.load()
+    return binding
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = np.linalg.norm((a - b).ravel())
+    n = np.linalg.norm(b.ravel())
+    return d / n if n > 0 else d
+
+
+def make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.01, lam=0.01, lr_core=None, lam_core=None,
+                seed=3001, chunk=0):
+    h = lib.Stdecomp(dims, ranks, idx, vals, batch=M, lr_factor=lr, lr_core=lr if lr_core is None else lr_core,
+                     lam_factor=lam, lam_core=lam if lam_core is None else lam_core, seed_sample=seed,
+                     init="caller", chunk=chunk)
+    h.set_params(A0, G0)
+    return h
+
+
+def compare_epochs(lib, oracle_mod, name, dims, ranks, idx, vals, M, epochs, lr=0.01, lam=0.01, seed=3001,
+                   chunk=0, init_seed=2001, test=None, tol=TOL):
+    """Run `epochs` epochs on the GPU; after each, run the oracle for the same
+    epoch from the GPU's starting state of that epoch and compare."""
+    A0, G0 = synth.init_params(dims, ranks, seed=init_seed)
+    say(name, "dims", dims, "ranks", ranks, "T", idx.shape[1], "M", M, "chunk", chunk)
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr, lam, seed=seed, chunk=chunk)
+    info = h.info()
+    say(name, "chain", info)
+    free_run = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    A_start, G_start = A0, G0
+    worst = 0.0
+    for e in range(epochs):
+        say(name, "epoch", e)
+        h.epoch(1)
+        Ag, Gg = h.get_params()
+        ref = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A_start], G_start.astype(np.float64))
+        ref.run(idx, vals, M, lr, lam, lr, lam, seed=seed, epoch0=e, n_epochs=1)
+        errs = [rel(Ag[n], ref.A[n]) for n in range(len(dims))] + [rel(Gg, ref.G)]
+        worst = max(worst, max(errs))
+        assert max(errs) <= tol, (name, e, errs)
+        if test is not None:
+            rg = h.loss(test[0], test[1])["rmse"]
+            ro = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in Ag],
+                                  Gg.astype(np.float64)).loss(test[0], test[1])["rmse"]
+            assert abs(rg - ro) <= tol * ro, (name, e, rg, ro)
+        free_run.run(idx, vals, M, lr, lam, lr, lam, seed=seed, epoch0=e, n_epochs=1)
+        A_start, G_start = Ag, Gg
+    drift = max([rel(Ag[n], free_run.A[n]) for n in range(len(dims))] + [rel(Gg, free_run.G)])
+    say(name, "worst per-epoch rel err %.3g, free-running drift after %d epochs %.3g" % (worst, epochs, drift))
+    h.close()
+    return worst, drift
+
+
+# ----------------------------------------------------------------- sampler
+@pytest.mark.parametrize("T", [1, 2, 3, 17, 1000, 65537, 1 << 20, (1 << 20) + 1])
+def test_sampler_bit_exact(lib, oracle_mod, T):
+    for seed, epoch in ((0, 0), (3001, 5), (0xDEADBEEFCAFE, 123)):
+        say("sampler T", T, "seed", seed, "epoch", epoch)
+        np.testing.assert_array_equal(lib.sample_order(T, seed, epoch), oracle_mod.perm(T, seed, epoch))
+
+
+def test_sampler_golden_vectors(lib):
+    import json
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sampler_vectors.json")))
+    for c in g["cases"]:
+        say("sampler golden", c["T"], c["seed"], c["epoch"])
+        p = lib.sample_order(c["T"], c["seed"], c["epoch"])
+        assert p[: len(c["head"])].tolist() == c["head"]
+
+
+# ------------------------------------------------------- schedule (integers)
+@pytest.mark.parametrize("skew", [None, 1.2])
+def test_schedule_bit_exact(lib, oracle_mod, skew):
+    dims, ranks = (300, 50, 7), (3, 2, 2)
+    idx, vals = synth.random_tiny(3, dims, ranks, 10_007, seed=5, skew=skew)
+    M = 1000
+    A0, G0 = synth.init_params(dims, ranks, seed=1)
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, seed=77, chunk=64)
+    T = idx.shape[1]
+    for epoch in (0, 3):
+        order = oracle_mod.perm(T, 77, epoch)
+        for b in (0, 4, T // M):  # includes the ragged last minibatch
+            for mode in range(3):
+                say("schedule skew", skew, "epoch", epoch, "batch", b, "mode", mode)
+                got = h.debug_schedule(epoch, b, mode)
+                ent = order[b * M: min((b + 1) * M, T)]
+                np.testing.assert_array_equal(got["entries"], ent)
+                sigma, off, segrow = oracle_mod.segments(idx[mode][ent])
+                np.testing.assert_array_equal(got["sigma"], sigma)
+                np.testing.assert_array_equal(got["seg_off"], off)
+                np.testing.assert_array_equal(got["seg_row"], segrow)
+    h.close()
+
+
+# ---------------------------------------------------------- predict / loss
+@pytest.mark.parametrize("dims,ranks", [((40, 30, 20), (4, 4, 4)), ((10, 12, 9, 8), (2, 3, 2, 3)),
+                                        ((7, 6), (5, 7)), ((9, 8, 7, 6, 5), (2, 2, 2, 2, 2)),
+                                        ((50, 40, 30), (10, 10, 10)), ((20, 20, 20), (16, 16, 16))])
+def test_predict_and_loss(lib, oracle_mod, dims, ranks):
+    say("predict", dims, ranks)
+    rng = np.random.default_rng(3)
+    A = [rng.standard_normal((I, J)).astype(np.float32) / np.sqrt(J) for I, J in zip(dims, ranks)]
+    G = (rng.standard_normal(int(np.prod(ranks))) / np.sqrt(ranks[0])).astype(np.float32)
+    idx, vals = synth.random_tiny(len(dims), dims, ranks, 5000, seed=4)
+    h = make_handle(lib, dims, ranks, idx, vals, A, G, 64)
+    ref = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A], G.astype(np.float64))
+    q = np.stack([rng.integers(0, I, 3001) for I in dims]).astype(np.int32)
+    got = h.predict(q)
+    want = ref.predict(q)
+    scale = np.sqrt(np.mean(want ** 2))
+    assert np.max(np.abs(got - want)) <= 1e-5 * max(scale, 1e-3)
+    lg, lo = h.loss(q, vals[:3001]), ref.loss(q, vals[:3001], lam_A=0.01, lam_G=0.01)
+    for k in ("rmse", "mae", "sse", "objective"):
+        assert abs(lg[k] - lo[k]) <= 1e-5 * abs(lo[k]), k
+    tr = h.loss()
+    assert tr["count"] == idx.shape[1]
+    assert abs(tr["rmse"] - ref.loss(idx, vals)["rmse"]) <= 1e-5 * ref.loss(idx, vals)["rmse"]
+    h.close()
+
+
+def test_predict_rejects_bad_index(lib):
+    say("predict bad index")
+    dims, ranks = (10, 10, 10), (2, 2, 2)
+    idx, vals = synth.random_tiny(3, dims, ranks, 100, seed=1)
+    A0, G0 = synth.init_params(dims, ranks, seed=1)
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, 16)
+    bad = np.array([[0, 1], [0, 10], [0, 1]], np.int32)
+    with pytest.raises(lib.StdecompError) as ei:
+        h.predict(bad)
+    assert ei.value.code == lib.STD_E_INVAL
+    h.close()
+
+
+def test_init_rejects_bad_problem(lib):
+    say("init bad problem")
+    dims, ranks = (10, 10, 10), (2, 2, 2)
+    idx, vals = synth.random_tiny(3, dims, ranks, 100, seed=1)
+    idx[1, 5] = 10
+    with pytest.raises(lib.StdecompError):
+        lib.Stdecomp(dims, ranks, idx, vals, batch=16)
+    idx[1, 5] = 0
+    with pytest.raises(lib.StdecompError):
+        lib.Stdecomp(dims, (2, 2, 33), idx, vals, batch=16)
+    with pytest.raises(lib.StdecompError):
+        lib.Stdecomp(dims, ranks, idx, vals, batch=0)
+
+
+# ------------------------------------------------------- the SGD epochs
+CASES = [
+    # name, dims, ranks, nnz, M, chunk, skew
+    ("n3_mixed_generic_w4", (60, 50, 40), (2, 3, 4), 3000, 32, 8, None),
+    ("n2_uniform_w1", (80, 70), (4, 4), 4000, 64, 0, None),
+    ("n4_uniform_w8", (30, 25, 20, 15), (3, 3, 3, 3), 5000, 128, 16, None),
+    ("n5_uniform", (12, 11, 10, 9, 8), (2, 2, 2, 2, 2), 3000, 64, 16, None),
+    ("n3_zipf_long_runs_w8", (500, 400, 30), (4, 4, 4), 30000, 512, 64, 1.3),
+    ("n3_j10_w4_ragged", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
+    ("n3_j16", (100, 90, 80), (16, 16, 16), 6000, 256, 64, None),
+    ("n3_j5_chunk1", (50, 40, 30), (5, 5, 5), 700, 8, 1, 1.5),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_epochs_match_oracle(lib, oracle_mod, case):
+    name, dims, ranks, nnz, M, chunk, skew = case
+    idx, vals = synth.random_tiny(len(dims), dims, ranks, nnz, seed=len(name), skew=skew)
+    vals = (vals * 0.5).astype(np.float32)
+    compare_epochs(lib, oracle_mod, name, dims, ranks, idx, vals, M, epochs=3, lr=0.02, lam=0.01, chunk=chunk)
+
+
+def test_planted_config_c1(lib, oracle_mod):
+    """The small planted workload: 1000^3, 100k entries (10% held out), J = 5,
+    M = 256, lr = lambda = 0.01, 10 epochs; per-epoch parameters and held-out
+    RMSE against the oracle."""
+    wl = synth.planted_uniform(seed=1001)
+    compare_epochs(lib, oracle_mod, "c1", wl.dims, wl.ranks, wl.train_idx, wl.train_vals, 256, epochs=10,
+                   lr=0.01, lam=0.01, test=(wl.test_idx, wl.test_vals))
+
+
+def test_deterministic_and_resumable(lib):
+    dims, ranks = (200, 150, 100), (4, 4, 4)
+    idx, vals = synth.random_tiny(3, dims, ranks, 20000, seed=9, skew=1.2)
+    A0, G0 = synth.init_params(dims, ranks, seed=9)
+    say("determinism")
+    runs = []
+    for _ in range(2):
+        h = make_handle(lib, dims, ranks, idx, vals, A0, G0, 512, chunk=64)
+        h.epoch(2)
+        runs.append(h.get_params())
+        h.close()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    say("resume at epoch 1")
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, 512, chunk=64)
+    h.epoch(1)
+    A1, G1 = h.get_params()
+    h.close()
+    h = make_handle(lib, dims, ranks, idx, vals, A1, G1, 512, chunk=64)
+    h.set_epoch(1)
+    h.epoch(1)
+    A2, G2 = h.get_params()
+    h.close()
+    for a, b in zip(A2, runs[0][0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(G2, runs[0][1])
+    say("resume mid-epoch")
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, 512, chunk=64)
+    nb = h.info()["minibatches"]
+    h.run_minibatches(0, 0, 7)
+    h.run_minibatches(0, 7, nb)
+    h.run_minibatches(1, 0, nb)
+    A3, G3 = h.get_params()
+    h.close()
+    for a, b in zip(A3, runs[0][0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(G3, runs[0][1])
+
+
+def test_diverged_is_reported(lib):
+    say("divergence")
+    dims, ranks = (20, 20, 20), (3, 3, 3)
+    idx, vals = synth.random_tiny(3, dims, ranks, 2000, seed=2)
+    A0, G0 = synth.init_params(dims, ranks, seed=2)
+    A0 = [a * 5 for a in A0]
+    h = make_handle(lib, dims, ranks, idx, vals * 100, A0, G0 * 5, 16, lr=5.0, lam=0.0)
+    with pytest.raises(lib.StdecompError) as ei:
+        for _ in range(5):
+            h.epoch(1)
+    assert ei.value.code == lib.STD_E_DIVERGED
+    h.close()
