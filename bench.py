@@ -1,0 +1,188 @@
+"""Throughput of the SGD_Tucker minibatch update on one MI355X.
+
+Workload: the Netflix-shaped rating tensor -- 480000 x 18000 x 2000, 100M
+nonzeros with Zipf(1.1) indices per mode and ratings 1..5, 10% held out --
+with core ranks J = (10, 10, 10) and minibatches of M = 4096 (synthetic data,
+random initial parameters).  One step = one epoch over the ~90M training
+entries (sampler, row-set sort, minibatch chain) followed by the held-out
+RMSE.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--dtype f32|bf16]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_TFs": 157.3,
+    "bf16_TFs": 2500.0,
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--nnz", type=int, default=100_000_000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-batches", type=int, default=60,
+                    help="minibatches of the CPU oracle baseline (0: skip)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "chain_traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 5}))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2012_03550_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t = time.time()
+    wl = synth.ratings_zipf(nnz=args.nnz)
+    log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
+    M = args.batch
+    lr = lam = 0.01
+    h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
+                         lam_factor=lam, lam_core=lam, seed_sample=3002, seed_init=2002, dtype=args.dtype,
+                         chunk=args.chunk)
+    info = h.info()
+    log("chain", info)
+    A0, G0 = h.get_params()
+    test_idx = torch.from_numpy(wl.test_idx).cuda()
+    test_vals = torch.from_numpy(wl.test_vals).cuda()
+
+    for w in range(args.warmup):
+        st = h.epoch(1)
+        h.loss(test_idx, test_vals)
+        log("warmup epoch %d: %.3fs device" % (w, st["device_seconds"]))
+    torch.cuda.synchronize()
+    acc = None
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = h.epoch(1)
+        ls = h.loss(test_idx, test_vals)
+        if acc is None:
+            acc = dict(st)
+        else:
+            for key in st:
+                acc[key] += st[key]
+        log("step %d: chain %.3fs schedule %.4fs held-out RMSE %.5f" % (k, st["chain_seconds"],
+                                                                       st["schedule_seconds"], ls["rmse"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    updates = acc["updates"]
+    value = updates / elapsed
+
+    # roofline of the dominant kernel (the minibatch chain), from the
+    # library's HIP events on its own stream
+    launches = acc["chain_launches"]
+    avg_launch = acc["chain_seconds"] / launches
+    flops_per_launch = acc["flops_alg"] / launches
+    achieved = flops_per_launch / avg_launch / 1e12
+    peak = PEAK["bf16_TFs"] if args.dtype == "bf16" else PEAK["fp32_TFs"]
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        tj = json.load(open(args.traffic_json))
+        if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("dtype") == args.dtype:
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "mfma" if args.dtype == "bf16" else "alu", "achieved": round(achieved, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6), "traffic": traffic,
+                "kernel": "k_chain", "avg_launch_ms": round(avg_launch * 1e3, 3),
+                "hbm_alg_GBs": round(acc["bytes_alg"] / acc["chain_seconds"] / 1e9, 2)}
+
+    cpu = None
+    if args.cpu_batches > 0:
+        cpu = cpu_baseline(h, wl, A0, G0, M, lr, lam, args.cpu_batches)
+    h.close()
+
+    out = {
+        "metric": "nonzero-updates/sec/GPU at fixed held-out RMSE",
+        "value": round(value, 1),
+        "unit": "nonzero-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "ratings_zipf 480000x18000x2000 100M nnz (Zipf 1.1, ratings 1-5, 10% held out), "
+                               "J=(10,10,10), M=4096, lr=lambda=0.01; step = 1 epoch + held-out RMSE",
+                   "train_entries": int(wl.nnz), "batch": M, "chain_workgroups": info["workgroups"],
+                   "chain_chunk": info["chunk"]},
+        "heldout_rmse": round(ls["rmse"], 6),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in ("stdecomp_chain.hip", "stdecomp_device.h", "stdecomp_internal.h"):
+        hsh.update(open(os.path.join(ROOT, "paper_2012_03550_amd", "csrc", f), "rb").read())
+    return hsh.hexdigest()[:16]
+
+
+def cpu_baseline(h, wl, A0, G0, M, lr, lam, nbatches):
+    """The FP64 oracle (single thread) on the first `nbatches` minibatches of
+    epoch 0 from the same initial parameters, plus the GPU's result on the
+    same prefix for a parity check."""
+    import numpy as np
+    from oracle import oracle
+    from paper_2012_03550_amd import binding
+    oracle.build()
+    ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    t = time.perf_counter()
+    ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3002, epoch0=0, n_epochs=1,
+            max_batches=nbatches)
+    dt = time.perf_counter() - t
+    g = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
+                         lam_factor=lam, lam_core=lam, seed_sample=3002, init="caller")
+    g.set_params(A0, G0)
+    g.run_minibatches(0, 0, nbatches)
+    Ag, Gg = g.get_params()
+    g.close()
+    err = max([float(np.linalg.norm(Ag[n] - ref.A[n]) / np.linalg.norm(ref.A[n])) for n in range(3)] +
+              [float(np.linalg.norm(Gg - ref.G) / np.linalg.norm(ref.G))])
+    log("cpu oracle: %d minibatches in %.2fs; GPU vs oracle on that prefix: max rel err %.3g" % (nbatches, dt, err))
+    return {"value": round(nbatches * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d minibatches (%d updates) of epoch 0 from the same initial parameters, FP64 C, "
+                      "one thread" % (nbatches, nbatches * M),
+            "gpu_prefix_max_rel_err": err}
+
+
+if __name__ == "__main__":
+    main()

@@ -11,6 +11,7 @@ constexpr int kMaxRank = 32;      // largest J_n the kernels accept
 constexpr int kMaxBatch = 16384;  // largest minibatch (positions are 16-bit)
 constexpr int kChainThreads = 256;
 constexpr int kSortThreads = 256;
+constexpr int kFlagStride = 16;   // words between two workgroups' barrier flags (64 bytes)
 
 // Round x up to a multiple of 4 floats (16-byte factor rows).
 __host__ __device__ inline int pad4(int x) { return (x + 3) & ~3; }
@@ -25,6 +26,17 @@ struct Shape {
   int R;                 // words per COO record: N indices then the value bits
   int rs_off[kMaxOrder]; // offset of mode k's row inside an LDS row buffer
   int rs;                // LDS row-buffer stride per sample (odd, avoids bank conflicts)
+  int lstride[kMaxOrder];// stride of j_k in the flat core: prod_{k' < k} J_k'
+};
+
+// LDS regions of a chain workgroup (float offsets) and strides.
+struct ChainLayout {
+  int gs, tb, row, hp, ebuf, ra, split, cbuf, hmap, wscr, ints, total;
+  int chp;      // chunk rounded up to 16 (MFMA tile rows)
+  int es;       // stride of the E buffer (odd)
+  int ras;      // stride of the r * a(0) buffer
+  int sstride;  // stride of the split-row table
+  int wstride;  // stride of the per-wave scan tails
 };
 
 // Arguments of the persistent minibatch chain kernel.
@@ -32,14 +44,16 @@ struct ChainArgs {
   Shape s;
   const uint32_t* coo;      // records in epoch order (T x R words)
   const uint16_t* sigma;    // [N][T] per-minibatch sorted positions
+  const uint32_t* rec_sorted; // [N][T] records in (row, position) order per minibatch
   const int* xrow;          // [nb][N][W] row straddling each chunk boundary, or -1
   float* A[kMaxOrder];      // FP32 master factors, I_n x Jp_n
-  uint16_t* Ab[kMaxOrder];  // BF16 read copies (null in FP32 mode)
+  uint16_t* Ab[kMaxOrder];  // BF16 read copies (null in FP32 mode), I_n x Jb_n
+  int Jb[kMaxOrder];        // row stride of the BF16 copies (J_n rounded up to 8)
+  int bf16;                 // 1: BF16 operands, FP32 masters and accumulation
   float* G;                 // FP32 master core (P)
-  uint16_t* Gb;             // BF16 read copy of the core (null in FP32 mode)
-  float* partial;           // [W][P] per-workgroup core-gradient partials
+  float* partial;           // [W][pad4(P)] per-workgroup core-gradient partials
   float* carry;             // [2][W][2][carry_stride] per-chunk run partials and old rows
-  unsigned* bar;            // grid-barrier arrival counter (zero at launch)
+  unsigned* bar;            // grid-barrier arrival flags, one per workgroup, kFlagStride apart (zero at launch)
   int* err;                 // set to nonzero by a workgroup that gives up
   int64_t T, M;
   int64_t b_begin, b_end;   // minibatches [b_begin, b_end) of the epoch
@@ -48,9 +62,8 @@ struct ChainArgs {
   int chunk;                // samples per workgroup per phase (<= blockDim)
   int carry_stride;         // floats per carry slot
   long long spin_limit;     // barrier give-up bound (iterations)
-  int grad_groups;          // sample groups of the core-gradient pass
-  int gt_floats;            // LDS floats reserved for the unfolded-core table
   int split_cap;            // entries of the LDS split-row table
+  ChainLayout lay;          // filled by plan_chain_lds
 };
 
 // Which J specialisation of the chain serves a shape: the common rank when
@@ -61,11 +74,13 @@ int chain_variant(const Shape& s);
 hipError_t launch_perm_gather(const Shape& s, const uint32_t* coo, uint32_t* coo_perm, int64_t T,
                               uint64_t seed, int64_t epoch, hipStream_t st);
 hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, hipStream_t st);
-hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg, int W,
-                       int chunk, int64_t T, int64_t M, int64_t b_begin, int64_t b_end, hipStream_t st);
+hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg,
+                       uint32_t* rec_sorted, int W, int chunk, int64_t T, int64_t M, int64_t b_begin, int64_t b_end,
+                       hipStream_t st);
 hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const uint16_t* sigma,
                                  int64_t T, int64_t M, int64_t b, int mode, int32_t* seg_off,
                                  int32_t* seg_row, int32_t* nseg, hipStream_t st);
+size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16);
 size_t chain_lds_bytes(const ChainArgs& a, int threads);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
@@ -80,5 +95,8 @@ hipError_t launch_loss(const Shape& s, const uint32_t* rec, int64_t n, FactorPtr
 hipError_t launch_sumsq(const float* p, int64_t n, double* block_out, int nblocks, hipStream_t st);
 hipError_t launch_count_nonfinite(const float* p, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
+// rows x cols FP32 (row stride sstride) -> BF16 (row stride dstride), round to nearest even
+hipError_t launch_rows_to_bf16(const float* src, int sstride, uint16_t* dst, int dstride, int64_t rows, int cols,
+                               hipStream_t st);
 
 }  // namespace stdk

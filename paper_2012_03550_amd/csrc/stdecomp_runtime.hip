@@ -28,15 +28,19 @@ struct stdecomp_handle {
   int device = 0;
   int num_cus = 0;
   // chain configuration
-  int W = 1, chunk = 1, threads = 64, grad_groups = 1, gt_floats = 0, split_cap = 0, carry_stride = 0;
+  int W = 1, chunk = 1, threads = 64, split_cap = 0, carry_stride = 0;
   size_t chain_lds = 0;
+  stdk::ChainLayout lay{};
   // device buffers
   uint32_t* coo = nullptr;
   uint32_t* coo_perm = nullptr;
   uint16_t* sigma = nullptr;
+  uint32_t* rec_sorted = nullptr;
   int* xrow = nullptr;
   int* nseg = nullptr;
   float* A[kMaxOrder] = {};
+  uint16_t* Ab[kMaxOrder] = {};  // BF16 read copies (BF16 mode)
+  int Jb[kMaxOrder] = {};
   float* G = nullptr;
   float* partial = nullptr;
   float* carry = nullptr;
@@ -111,12 +115,9 @@ struct HostRng {
 
 int64_t total_minibatches(int64_t T, int64_t M) { return (T + M - 1) / M; }
 
-int chain_threads_for(int chunk) {
-  int t = ((chunk + 63) / 64) * 64;
-  if (t < 64) t = 64;
-  if (t > stdk::kChainThreads) t = stdk::kChainThreads;
-  return t;
-}
+// Four waves per chain workgroup whatever the chunk: the MFMA tiles and
+// table builds use all of them, the per-sample steps the first `chunk` lanes.
+int chain_threads_for(int /*chunk*/) { return stdk::kChainThreads; }
 
 // Pick the chain geometry and check that it fits one workgroup's LDS.
 int configure_chain(stdecomp_handle* h, int chunk_req) {
@@ -135,17 +136,6 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
   h->chunk = chunk;
   h->W = W;
   h->threads = chain_threads_for(chunk);
-  const int K0 = s.P / s.J[0];
-  int groups = h->threads / K0;
-  if (groups < 1) groups = 1;
-  if (groups > 8) groups = 8;
-  h->grad_groups = groups;
-  int gtf = 0;
-  for (int n = 0; n < s.N; ++n) {
-    const int f = (s.P / s.J[n]) * stdk::pad4(s.J[n]);
-    if (f > gtf) gtf = f;
-  }
-  h->gt_floats = gtf;
   h->split_cap = W > 1 ? W - 1 : 0;
   int jmax = 0;
   for (int n = 0; n < s.N; ++n) jmax = s.J[n] > jmax ? s.J[n] : jmax;
@@ -153,10 +143,12 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
   stdk::ChainArgs a{};
   a.s = s;
   a.W = W;
-  a.grad_groups = groups;
-  a.gt_floats = gtf;
+  a.chunk = chunk;
   a.split_cap = h->split_cap;
-  h->chain_lds = stdk::chain_lds_bytes(a, h->threads);
+  a.carry_stride = h->carry_stride;
+  h->chain_lds = stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16);
+  if (h->chain_lds == 0) return fail(h, STD_E_INVAL, "inconsistent chain plan");
+  h->lay = a.lay;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
     return fail(h, STD_E_DEVICE, "hipGetDeviceProperties failed");
@@ -173,8 +165,15 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.s = h->s;
   a.coo = h->coo_perm;
   a.sigma = h->sigma;
+  a.rec_sorted = h->rec_sorted;
   a.xrow = h->xrow;
-  for (int n = 0; n < h->s.N; ++n) a.A[n] = h->A[n];
+  for (int n = 0; n < h->s.N; ++n) {
+    a.A[n] = h->A[n];
+    a.Ab[n] = h->Ab[n];
+    a.Jb[n] = h->Jb[n];
+  }
+  a.bf16 = h->dtype == STD_DTYPE_BF16 ? 1 : 0;
+  a.lay = h->lay;
   a.G = h->G;
   a.partial = h->partial;
   a.carry = h->carry;
@@ -190,16 +189,14 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.chunk = h->chunk;
   a.carry_stride = h->carry_stride;
   a.spin_limit = kSpinLimit;
-  a.grad_groups = h->grad_groups;
-  a.gt_floats = h->gt_floats;
   a.split_cap = h->split_cap;
   return a;
 }
 
 int run_schedule(stdecomp_handle* h, int64_t epoch) {
   HIPCHK(h, stdk::launch_perm_gather(h->s, h->coo, h->coo_perm, h->T, h->seed_sample, epoch, h->stream));
-  HIPCHK(h, stdk::launch_sort(h->s, h->coo_perm, h->sigma, h->xrow, h->nseg, h->W, h->chunk, h->T, h->M, 0, h->nb,
-                              h->stream));
+  HIPCHK(h, stdk::launch_sort(h->s, h->coo_perm, h->sigma, h->xrow, h->nseg, h->rec_sorted, h->W, h->chunk, h->T,
+                              h->M, 0, h->nb, h->stream));
   h->sched_epoch = epoch;
   return STD_OK;
 }
@@ -289,14 +286,27 @@ int device_sumsq(stdecomp_handle* h, const float* p, int64_t n, double* out) {
   return STD_OK;
 }
 
+// BF16 read copies from the FP32 masters (BF16 mode only).
+int refresh_bf16(stdecomp_handle* h) {
+  if (h->dtype != STD_DTYPE_BF16) return STD_OK;
+  for (int n = 0; n < h->s.N; ++n)
+    HIPCHK(h, stdk::launch_rows_to_bf16(h->A[n], h->s.Jp[n], h->Ab[n], h->Jb[n], h->s.I[n], h->s.J[n], h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return STD_OK;
+}
+
 void release(stdecomp_handle* h) {
   if (!h) return;
   dfree(h->coo);
   dfree(h->coo_perm);
   dfree(h->sigma);
+  dfree(h->rec_sorted);
   dfree(h->xrow);
   dfree(h->nseg);
-  for (int n = 0; n < kMaxOrder; ++n) dfree(h->A[n]);
+  for (int n = 0; n < kMaxOrder; ++n) {
+    dfree(h->A[n]);
+    dfree(h->Ab[n]);
+  }
   dfree(h->G);
   dfree(h->partial);
   dfree(h->carry);
@@ -351,7 +361,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       !finite_nonneg(o->lambda_core))
     return STD_E_INVAL;
   if (o->init_kind < STD_INIT_SCALED || o->init_kind > STD_INIT_CALLER) return STD_E_INVAL;
-  if (o->dtype != STD_DTYPE_F32) return STD_E_INVAL;  // BF16 path: see stdecomp_bf16 (not in this build yet)
+  if (o->dtype != STD_DTYPE_F32 && o->dtype != STD_DTYPE_BF16) return STD_E_INVAL;
   if (o->r_core != 0) return STD_E_INVAL;
   for (int i = 0; i < 15; ++i)
     if (o->reserved[i] != 0) return STD_E_INVAL;
@@ -397,6 +407,13 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     off += s.J[n];
   }
   s.rs = off | 1;
+  {
+    int acc = 1;
+    for (int n = 0; n < N; ++n) {
+      s.lstride[n] = acc;
+      acc *= s.J[n];
+    }
+  }
   h->T = p->nnz;
   h->M = o->batch;
   h->nb = total_minibatches(h->T, h->M);
@@ -426,13 +443,17 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   // device memory
   const size_t T = (size_t)h->T;
   if ((rc = dalloc(h, &h->coo, T * s.R)) || (rc = dalloc(h, &h->coo_perm, T * s.R)) ||
-      (rc = dalloc(h, &h->sigma, T * N)) || (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * h->W)) ||
+      (rc = dalloc(h, &h->sigma, T * N)) || (rc = dalloc(h, &h->rec_sorted, T * N * s.R)) ||
+      (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * h->W)) ||
       (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
-      (rc = dalloc(h, &h->partial, (size_t)h->W * P)) ||
-      (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) || (rc = dalloc(h, &h->bar, 1)) ||
+      (rc = dalloc(h, &h->partial, (size_t)h->W * stdk::pad4((int)P))) ||
+      (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||
+      (rc = dalloc(h, &h->bar, (size_t)h->W * stdk::kFlagStride)) ||
       (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) || (rc = dalloc(h, &h->flag, 1)))
     return bail(rc);
   for (int n = 0; n < N; ++n) {
+    h->Jb[n] = (s.J[n] + 7) & ~7;
+    if (h->dtype == STD_DTYPE_BF16 && (rc = dalloc(h, &h->Ab[n], (size_t)s.I[n] * h->Jb[n]))) return bail(rc);
     if ((rc = dalloc(h, &h->A[n], (size_t)s.I[n] * s.Jp[n]))) return bail(rc);
     if (hipMemsetAsync(h->A[n], 0, (size_t)s.I[n] * s.Jp[n] * 4, h->stream) != hipSuccess) {
       h->last_error = "hipMemset failed";
@@ -511,6 +532,11 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       return bail(STD_E_DEVICE);
     }
   }
+  if (hipMemsetAsync(h->partial, 0, (size_t)h->W * stdk::pad4((int)P) * 4, h->stream) != hipSuccess ||
+      refresh_bf16(h) != STD_OK) {
+    h->last_error = "initialising device buffers failed";
+    return bail(STD_E_DEVICE);
+  }
   *out = h;
   return STD_OK;
 }
@@ -534,7 +560,7 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
   for (int64_t c0 = b0; c0 < b1; c0 += kBatchesPerLaunch) {
     a.b_begin = c0;
     a.b_end = (c0 + kBatchesPerLaunch < b1) ? c0 + kBatchesPerLaunch : b1;
-    HIPCHK(h, hipMemsetAsync(h->bar, 0, sizeof(unsigned), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h->stream));
     HIPCHK(h, stdk::launch_chain(a, h->threads, h->stream));
     acc->chain_launches++;
   }
@@ -700,7 +726,7 @@ int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* 
   }
   HIPCHK(h, hipMemcpyAsync(h->G, G, (size_t)h->s.P * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  return STD_OK;
+  return refresh_bf16(h);
 }
 
 int stdecomp_set_epoch(stdecomp_handle* h, int64_t e) {

@@ -42,21 +42,21 @@ def rel(a, b):
 
 
 def make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.01, lam=0.01, lr_core=None, lam_core=None,
-                seed=3001, chunk=0):
+                seed=3001, chunk=0, dtype="f32"):
     h = lib.Stdecomp(dims, ranks, idx, vals, batch=M, lr_factor=lr, lr_core=lr if lr_core is None else lr_core,
                      lam_factor=lam, lam_core=lam if lam_core is None else lam_core, seed_sample=seed,
-                     init="caller", chunk=chunk)
+                     init="caller", chunk=chunk, dtype=dtype)
     h.set_params(A0, G0)
     return h
 
 
 def compare_epochs(lib, oracle_mod, name, dims, ranks, idx, vals, M, epochs, lr=0.01, lam=0.01, seed=3001,
-                   chunk=0, init_seed=2001, test=None, tol=TOL):
+                   chunk=0, init_seed=2001, test=None, tol=TOL, dtype="f32", rmse_tol=None):
     """Run `epochs` epochs on the GPU; after each, run the oracle for the same
     epoch from the GPU's starting state of that epoch and compare."""
     A0, G0 = synth.init_params(dims, ranks, seed=init_seed)
     say(name, "dims", dims, "ranks", ranks, "T", idx.shape[1], "M", M, "chunk", chunk)
-    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr, lam, seed=seed, chunk=chunk)
+    h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr, lam, seed=seed, chunk=chunk, dtype=dtype)
     info = h.info()
     say(name, "chain", info)
     free_run = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
@@ -75,11 +75,19 @@ def compare_epochs(lib, oracle_mod, name, dims, ranks, idx, vals, M, epochs, lr=
             rg = h.loss(test[0], test[1])["rmse"]
             ro = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in Ag],
                                   Gg.astype(np.float64)).loss(test[0], test[1])["rmse"]
-            assert abs(rg - ro) <= tol * ro, (name, e, rg, ro)
+            assert abs(rg - ro) <= TOL * ro, (name, e, rg, ro)
         free_run.run(idx, vals, M, lr, lam, lr, lam, seed=seed, epoch0=e, n_epochs=1)
         A_start, G_start = Ag, Gg
     drift = max([rel(Ag[n], free_run.A[n]) for n in range(len(dims))] + [rel(Gg, free_run.G)])
-    say(name, "worst per-epoch rel err %.3g, free-running drift after %d epochs %.3g" % (worst, epochs, drift))
+    say(name, dtype, "worst per-epoch rel err %.3g, free-running drift after %d epochs %.3g" % (worst, epochs, drift))
+    gap = None
+    if test is not None:
+        rg = h.loss(test[0], test[1])["rmse"]
+        ro = free_run.loss(test[0], test[1])["rmse"]
+        gap = (rg - ro) / ro
+        say(name, dtype, "held-out RMSE %.6f vs free-running FP64 oracle %.6f (relative gap %.3g)" % (rg, ro, gap))
+        if rmse_tol is not None:
+            assert abs(gap) <= rmse_tol, (name, rg, ro)
     h.close()
     return worst, drift
 
@@ -261,3 +269,37 @@ def test_diverged_is_reported(lib):
             h.epoch(1)
     assert ei.value.code == lib.STD_E_DIVERGED
     h.close()
+
+
+# ------------------------------------------------------------ BF16 mode
+# BF16 operands carry a relative rounding error of at most 2^-9 (round to
+# nearest even, 8 significant bits).  One SGD step changes a parameter by
+# gamma * (gradient), whose BF16 error is O(2^-9) of its size; over an epoch
+# the accumulated parameter error relative to the parameters stays well
+# below 2^-9 * (number of steps a row takes) * gamma * |grad| / |param|.  The
+# bound used, 1e-2 per epoch from a common state, is about 5 ulps of BF16.
+BF16_TOL = 1e-2
+BF_CASES = [
+    ("bf16_n3_j10_w4", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
+    ("bf16_n4_j8_w8", (40, 30, 20, 15), (8, 8, 8, 8), 8000, 512, 64, None),
+    ("bf16_n3_mixed_generic", (60, 50, 40), (2, 3, 20), 3000, 64, 16, 1.3),
+    ("bf16_n3_j16", (100, 90, 80), (16, 16, 16), 6000, 256, 64, None),
+]
+
+
+@pytest.mark.parametrize("case", BF_CASES, ids=[c[0] for c in BF_CASES])
+def test_bf16_epochs_close_to_oracle(lib, oracle_mod, case):
+    name, dims, ranks, nnz, M, chunk, skew = case
+    idx, vals = synth.random_tiny(len(dims), dims, ranks, nnz, seed=len(name), skew=skew)
+    vals = (vals * 0.5).astype(np.float32)
+    compare_epochs(lib, oracle_mod, name, dims, ranks, idx, vals, M, epochs=2, lr=0.02, lam=0.01, chunk=chunk,
+                   dtype="bf16", tol=BF16_TOL)
+
+
+def test_bf16_planted_rmse_gap(lib, oracle_mod):
+    """BF16 on the small planted workload (1000^3, 100k entries, J = 5,
+    M = 256, 10 epochs): the held-out RMSE gap to the free-running FP64
+    oracle is reported and must stay under 1%."""
+    wl = synth.planted_uniform(seed=1001)
+    compare_epochs(lib, oracle_mod, "c1_bf16", wl.dims, wl.ranks, wl.train_idx, wl.train_vals, 256, epochs=10,
+                   lr=0.01, lam=0.01, test=(wl.test_idx, wl.test_vals), dtype="bf16", tol=BF16_TOL, rmse_tol=1e-2)
