@@ -296,30 +296,54 @@ __device__ __forceinline__ void build_hmap(const Tiling& g, int* hmap) {
 // B-operand table of mode n, built from the core Gs:
 //   FP32: TB[((h * nt + t) * kp + k) * 16 + c]   = G_(n)[16t + c, k + J_lo h]
 //   BF16: TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(same)
-// (zero outside j_n < J_n, k < J_lo).  Thread (k, c) walks (h, t).
+// (zero outside j_n < J_n, k < J_lo).  A flat loop over table elements;
+// each thread issues its four core reads before its four table writes (the
+// two LDS arrays could alias as far as the compiler knows).
 template <bool BF>
 __device__ void build_tables(const Shape& s, int n, const Tiling& g, const float* Gs, const int* hmap, float* TB) {
   const int Jn = s.J[n];
-  const int pairs = g.kp * 16;
+  const int total = g.khi * g.nt * g.kp * 16;
   unsigned short* TB16 = reinterpret_cast<unsigned short*>(TB);
-  for (int kc = threadIdx.x; kc < pairs; kc += blockDim.x) {
-    const int k = kc >> 4, c = kc & 15;
-    const bool kin = k < g.jlo;
-    const int kofs = k * g.ls_lo;
-    for (int h = 0; h < g.khi; ++h) {
-      const int base = kofs + hmap[h];
-      for (int t = 0; t < g.nt; ++t) {
+  const int BT = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 4 * BT) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * BT;
+      v[u] = 0.f;
+      if (e < total) {
+        int k, c, ht;
+        if (BF) {  // e = (ht * 16 + c) * kp + k
+          k = e % g.kp;
+          const int r = e / g.kp;
+          c = r & 15;
+          ht = r >> 4;
+        } else {   // e = (ht * kp + k) * 16 + c
+          c = e & 15;
+          const int r = e >> 4;
+          k = r % g.kp;
+          ht = r / g.kp;
+        }
+        const int h = g.nt == 1 ? ht : ht / g.nt;
+        const int t = ht - h * g.nt;
         const int jn = 16 * t + c;
-        const float v = (kin && jn < Jn) ? Gs[base + jn * g.ls_n] : 0.f;
-        if (BF) TB16[((h * g.nt + t) * 16 + c) * g.kp + k] = bf16_bits(v);
-        else TB[((h * g.nt + t) * g.kp + k) * 16 + c] = v;
+        if (k < g.jlo && jn < Jn) v[u] = Gs[hmap[h] + k * g.ls_lo + jn * g.ls_n];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * BT;
+      if (e < total) {
+        if (BF) TB16[e] = bf16_bits(v[u]);
+        else TB[e] = v[u];
       }
     }
   }
 }
 
 // hp[h * chp + p] = prod over the remaining modes of the sample's rows at h
-// (1 when there are none); zero for positions p >= cnt.
+// (1 when there are none); zero for positions p >= cnt.  Reads are batched
+// ahead of the writes, four h at a time.
 __device__ __forceinline__ void build_hp(const Shape& s, const Tiling& g, const float* rowbuf, const int* hmap,
                                          int cnt, int chp, float* hp) {
   const int p = threadIdx.x;
@@ -328,16 +352,24 @@ __device__ __forceinline__ void build_hp(const Shape& s, const Tiling& g, const 
   const int* ro = hmap + g.khi;
   if (p >= cnt) {
     for (int h = 0; h < g.khi; ++h) hp[h * chp + p] = 0.f;
-  } else if (g.nhi == 0) {
+    return;
+  }
+  if (g.nhi == 0) {
     hp[p] = 1.f;
-  } else if (g.nhi == 1) {
-    for (int h = 0; h < g.khi; ++h) hp[h * chp + p] = rb[ro[h]];
-  } else {
-    for (int h = 0; h < g.khi; ++h) {
-      float v = 1.f;
-      for (int i = 0; i < g.nhi; ++i) v *= rb[ro[h * g.nhi + i]];
-      hp[h * chp + p] = v;
+    return;
+  }
+  for (int h0 = 0; h0 < g.khi; h0 += 4) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int h = h0 + u;
+      v[u] = 1.f;
+      if (h < g.khi)
+        for (int i = 0; i < g.nhi; ++i) v[u] *= rb[ro[h * g.nhi + i]];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (h0 + u < g.khi) hp[(h0 + u) * chp + p] = v[u];
   }
 }
 
@@ -373,7 +405,43 @@ __device__ void mfma_E(const Shape& s, int n, const Tiling& g, const float* TB, 
       const int nks = g.kp >> 2;
       const float* tb = TB + (t * g.kp + kq) * 16 + r16;
       const int hstride = g.nt * g.kp * 16;
-for (int h = 0; h < g.khi; ++h) {
+      int h = 0;
+      for (; h + 1 < g.khi; h += 2) {  // two h per iteration: four independent MFMA chains
+        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          if (ks < nks) {
+            const float bv = tb[h * hstride + ks * 64];
+            const float bw = tb[(h + 1) * hstride + ks * 64];
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, c1, 0, 0, 0);
+            d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bw, d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bw, d1, 0, 0, 0);
+          }
+        }
+        const float4 h0 = *reinterpret_cast<const float4*>(hp0 + h * chp);
+        const float4 g0 = *reinterpret_cast<const float4*>(hp0 + (h + 1) * chp);
+        const float4 h1 = has1 ? *reinterpret_cast<const float4*>(hp1 + h * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 g1 = has1 ? *reinterpret_cast<const float4*>(hp1 + (h + 1) * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
+        e0[0] = fmaf(c0[0], h0.x, e0[0]);
+        e0[1] = fmaf(c0[1], h0.y, e0[1]);
+        e0[2] = fmaf(c0[2], h0.z, e0[2]);
+        e0[3] = fmaf(c0[3], h0.w, e0[3]);
+        e1[0] = fmaf(c1[0], h1.x, e1[0]);
+        e1[1] = fmaf(c1[1], h1.y, e1[1]);
+        e1[2] = fmaf(c1[2], h1.z, e1[2]);
+        e1[3] = fmaf(c1[3], h1.w, e1[3]);
+        e0[0] = fmaf(d0[0], g0.x, e0[0]);
+        e0[1] = fmaf(d0[1], g0.y, e0[1]);
+        e0[2] = fmaf(d0[2], g0.z, e0[2]);
+        e0[3] = fmaf(d0[3], g0.w, e0[3]);
+        e1[0] = fmaf(d1[0], g1.x, e1[0]);
+        e1[1] = fmaf(d1[1], g1.y, e1[1]);
+        e1[2] = fmaf(d1[2], g1.z, e1[2]);
+        e1[3] = fmaf(d1[3], g1.w, e1[3]);
+      }
+      for (; h < g.khi; ++h) {
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -478,15 +546,27 @@ __device__ void mfma_core_grad(const Shape& s, const Tiling& g, const float* row
 #pragma unroll
     for (int q = 0; q < JG; ++q) c[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF) {
-      for (int st = 0; st < nsteps; ++st) {
+      // operands of step st+1 are read before the MFMAs of step st
+      auto load = [&](int st, float& rav, float& bv, float (&hv)[JG]) {
         const int p = st * 4 + kq;
-        const float rav = (arow && p < chp) ? ra[p * ras + j0] : 0.f;
-        const float bv = (bcol && p < cnt) ? rowbuf[p * s.rs + lo_off + jl] : 0.f;
+        rav = (arow && p < chp) ? ra[p * ras + j0] : 0.f;
+        bv = (bcol && p < cnt) ? rowbuf[p * s.rs + lo_off + jl] : 0.f;
 #pragma unroll
-        for (int q = 0; q < JG; ++q) {
-          const float av = (p < chp) ? rav * hph[q][p] : 0.f;
-          c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c[q], 0, 0, 0);
-        }
+        for (int q = 0; q < JG; ++q) hv[q] = (p < chp) ? hph[q][p] : 0.f;
+      };
+      float rav, bv, hv[JG];
+      if (nsteps > 0) load(0, rav, bv, hv);
+      for (int st = 0; st < nsteps; ++st) {
+        float rav2 = 0.f, bv2 = 0.f, hv2[JG];
+#pragma unroll
+        for (int q = 0; q < JG; ++q) hv2[q] = 0.f;
+        if (st + 1 < nsteps) load(st + 1, rav2, bv2, hv2);
+#pragma unroll
+        for (int q = 0; q < JG; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rav * hv[q], bv, c[q], 0, 0, 0);
+        rav = rav2;
+        bv = bv2;
+#pragma unroll
+        for (int q = 0; q < JG; ++q) hv[q] = hv2[q];
       }
     } else {
       for (int st = 0; st < nsteps; ++st) {
