@@ -18,12 +18,28 @@
 // FP32 mode uses v_mfma_f32_16x16x4_f32; BF16 mode rounds the operands to
 // BF16 (RNE) and uses v_mfma_f32_16x16x16_bf16, accumulating in FP32, with
 // BF16 read copies of the factors and FP32 masters receiving the updates.
+//
+// Latency plan of a sub-step (one workgroup of four waves per chunk, so
+// every dependent round trip to memory is exposed):
+//   * the rows a sub-step reads are loaded during the previous sub-step and
+//     parked in registers, except the rows of the modes updated by the two
+//     previous sub-steps; those, the previous sub-step's carried partial sums
+//     and the core partials are read in one batch after the barrier;
+//   * the B-operand tables of every mode depend only on the core and are
+//     rebuilt once per minibatch (right after the core update) when they fit
+//     in LDS; the index maps they need are built on the host;
+//   * the run structure of the (row, position) order (run starts, last
+//     positions, runs crossing chunk boundaries and their numbering) comes
+//     with the schedule, so the factor sub-step needs no search for it.
+#include <vector>
+
 #include "stdecomp_device.h"
 
 namespace stdk {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -40,7 +56,9 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 // read-modify-write on a shared word, so arrivals do not serialise.  Every
 // thread fences its global writes (agent scope) before the arrival; the wait
 // has a give-up bound so a lost workgroup can never hang the device (the
-// error flag then stops every workgroup).
+// error flag then stops every workgroup).  Arrival and wait are separate
+// calls so that work which reads nothing the other workgroups write can run
+// in between.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void barrier_arrive(const ChainArgs& a, unsigned passed) {
   __threadfence();
@@ -77,140 +95,159 @@ __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed
   return *flag_lds != 0;
 }
 
-// The record (N indices, value) a lane handles in phase ph of minibatch b:
-// minibatch order for the core sub-step, (row, position) order of mode ph-1
-// for the factor sub-steps.  Records are read-only during the chain, so they
-// are loaded before the barrier that opens the phase.
-__device__ __forceinline__ void load_phase_record(const ChainArgs& a, int64_t b, int ph,
-                                                  uint32_t (&rec)[kMaxOrder + 1]) {
+// ---------------------------------------------------------------------------
+// The record a lane handles in one phase: minibatch order for the core
+// sub-step, (row, position) order of mode ph-1 for the factor sub-steps.
+// Every field is read from memory at a uniform offset, so no register array
+// is ever indexed at run time.
+// ---------------------------------------------------------------------------
+struct LaneRec {
+  int idx[kMaxOrder];  // the N indices (only read at compile-time positions)
+  float x;             // the value
+  int rown;            // index in the phase's mode n
+  int rpm;             // index in the mode the previous phase updated (or -1)
+  int meta;            // run metadata (factor phases)
+  bool valid;
+};
+
+__device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int64_t b, int ph, LaneRec& r) {
+  const PhaseTab& pt = a.pt[ph];
   const int64_t base = b * a.M;
   const int m = (int)((a.T - base < a.M) ? (a.T - base) : a.M);
   const int q = blockIdx.x * a.chunk + (int)threadIdx.x;
-  if ((int)threadIdx.x < a.chunk && q < m) {
+  r.valid = (int)threadIdx.x < a.chunk && q < m;
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k) r.idx[k] = 0;
+  r.x = 0.f;
+  r.rown = 0;
+  r.rpm = -1;
+  r.meta = 0;
+  if (r.valid) {
     const uint32_t* src = (ph == 0) ? a.coo + (base + q) * a.s.R
                                     : a.rec_sorted + ((int64_t)(ph - 1) * a.T + base + q) * a.s.R;
 #pragma unroll
-    for (int w = 0; w < kMaxOrder + 1; ++w)
-      if (w < a.s.R) rec[w] = src[w];
+    for (int k = 0; k < kMaxOrder; ++k)
+      if (k < a.s.N) r.idx[k] = (int)src[k];
+    r.x = __uint_as_float(src[a.s.R - 1]);
+    r.rown = (int)src[pt.n];
+    if (pt.pm >= 0) r.rpm = (int)src[pt.pm];
+    if (ph > 0) r.meta = a.meta[(int64_t)(ph - 1) * a.T + base + q];
   }
 }
 
-// Copy the N rows of a sample into its LDS row buffer: all loads are issued
-// before the first LDS store (the read copies: FP32 masters, or BF16).
-template <int JR, bool BF>
-__device__ __forceinline__ void gather_sample_rows(const ChainArgs& a, const int (&idx)[kMaxOrder], float* rb) {
-  const Shape& s = a.s;
-  constexpr int STAGE = JR <= 16 ? 4 : 2;  // modes staged in registers at once
-  if constexpr (!BF) {
-    constexpr int C4 = (JR + 3) / 4;
-    for (int k0 = 0; k0 < s.N; k0 += STAGE) {
-      float4 st[STAGE][C4];
+// ---------------------------------------------------------------------------
+// Factor rows of one sample held in registers: slot i is mode K0 + i, as raw
+// 16-byte vectors of the read copy (4 FP32 or 8 BF16 values).
+// ---------------------------------------------------------------------------
+template <int JR, bool BF, int NS>
+struct RowRegs {
+  static constexpr int C = BF ? (JR + 7) / 8 : (JR + 3) / 4;
+  u32x4 v[NS > 0 ? NS : 1][C];
+};
+
+template <int JR, bool BF, int NS, int K0>
+__device__ __forceinline__ void issue_rows(const ChainArgs& a, const int (&idx)[kMaxOrder], unsigned mask,
+                                           RowRegs<JR, BF, NS>& rr) {
+  constexpr int C = RowRegs<JR, BF, NS>::C;
+  constexpr int PER = BF ? 8 : 4;
 #pragma unroll
-      for (int kk = 0; kk < STAGE; ++kk) {
-        const int k = k0 + kk;
-        int row = 0;
+  for (int i = 0; i < NS; ++i) {
+    const int k = K0 + i;
+    if (k < kMaxOrder && ((mask >> k) & 1u)) {
+      const u32x4* src = BF ? reinterpret_cast<const u32x4*>(a.Ab[k] + (int64_t)idx[k] * a.Jb[k])
+                            : reinterpret_cast<const u32x4*>(a.A[k] + (int64_t)idx[k] * a.s.Jp[k]);
 #pragma unroll
-        for (int t = 0; t < kMaxOrder; ++t)
-          if (t == k) row = idx[t];
-        if (k < s.N) {
-          const float4* src = reinterpret_cast<const float4*>(a.A[k] + (int64_t)row * s.Jp[k]);
+      for (int c = 0; c < C; ++c)
+        if (PER * c < a.s.J[k]) rr.v[i][c] = src[c];
+    }
+  }
+}
+
+template <int JR, bool BF, int NS, int K0>
+__device__ __forceinline__ void store_rows(const ChainArgs& a, unsigned mask, const RowRegs<JR, BF, NS>& rr,
+                                           float* rb) {
+  constexpr int C = RowRegs<JR, BF, NS>::C;
 #pragma unroll
-          for (int c = 0; c < C4; ++c)
-            if (4 * c < s.J[k]) st[kk][c] = src[c];
-        }
-      }
+  for (int i = 0; i < NS; ++i) {
+    const int k = K0 + i;
+    if (k < kMaxOrder && ((mask >> k) & 1u)) {
+      const int J = a.s.J[k];
+      float* dst = rb + a.s.rs_off[k];
 #pragma unroll
-      for (int kk = 0; kk < STAGE; ++kk) {
-        const int k = k0 + kk;
-        if (k < s.N) {
-          const int J = s.J[k];
-          float* dst = rb + s.rs_off[k];
+      for (int c = 0; c < C; ++c) {
+        const u32x4 w4 = rr.v[i][c];
+        if constexpr (!BF) {
 #pragma unroll
-          for (int c = 0; c < C4; ++c) {
-            if (4 * c < J) dst[4 * c] = st[kk][c].x;
-            if (4 * c + 1 < J) dst[4 * c + 1] = st[kk][c].y;
-            if (4 * c + 2 < J) dst[4 * c + 2] = st[kk][c].z;
-            if (4 * c + 3 < J) dst[4 * c + 3] = st[kk][c].w;
+          for (int e = 0; e < 4; ++e)
+            if (4 * c + e < J) dst[4 * c + e] = __uint_as_float(w4[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int j = 8 * c + e;
+            if (j < J) dst[j] = bf16_val((unsigned short)((e & 1) ? (w4[e >> 1] >> 16) : (w4[e >> 1] & 0xFFFFu)));
           }
         }
       }
     }
-  } else {
-    constexpr int C8 = (JR + 7) / 8;
-    for (int k0 = 0; k0 < s.N; k0 += STAGE) {
-      uint4 st[STAGE][C8];
-#pragma unroll
-      for (int kk = 0; kk < STAGE; ++kk) {
-        const int k = k0 + kk;
-        int row = 0;
-#pragma unroll
-        for (int t = 0; t < kMaxOrder; ++t)
-          if (t == k) row = idx[t];
-        if (k < s.N) {
-          const uint4* src = reinterpret_cast<const uint4*>(a.Ab[k] + (int64_t)row * a.Jb[k]);
-#pragma unroll
-          for (int c = 0; c < C8; ++c)
-            if (8 * c < s.J[k]) st[kk][c] = src[c];
-        }
-      }
-#pragma unroll
-      for (int kk = 0; kk < STAGE; ++kk) {
-        const int k = k0 + kk;
-        if (k < s.N) {
-          const int J = s.J[k];
-          float* dst = rb + s.rs_off[k];
-#pragma unroll
-          for (int c = 0; c < C8; ++c) {
-            const uint32_t w4[4] = {st[kk][c].x, st[kk][c].y, st[kk][c].z, st[kk][c].w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int j = 8 * c + e;
-              if (j < J) dst[j] = bf16_val((unsigned short)((e & 1) ? (w4[e >> 1] >> 16) : (w4[e >> 1] & 0xFFFFu)));
-            }
-          }
-        }
-      }
+  }
+}
+
+// All rows of `mask` for one sample into its LDS row buffer, staged so that
+// at most 16 vectors are in registers at once.
+template <int JR, bool BF>
+__device__ __forceinline__ void gather_rows(const ChainArgs& a, const int (&idx)[kMaxOrder], unsigned mask, float* rb) {
+  constexpr int C = RowRegs<JR, BF, 1>::C;
+  constexpr int SP = (16 / C) < kMaxOrder ? (16 / C) : kMaxOrder;
+  static_assert(4 * SP >= kMaxOrder, "four stages cover every mode");
+  RowRegs<JR, BF, SP> r0;
+  issue_rows<JR, BF, SP, 0>(a, idx, mask, r0);
+  store_rows<JR, BF, SP, 0>(a, mask, r0, rb);
+  if constexpr (SP < kMaxOrder) {
+    if (mask >> SP) {
+      RowRegs<JR, BF, SP> r1;
+      issue_rows<JR, BF, SP, SP>(a, idx, mask, r1);
+      store_rows<JR, BF, SP, SP>(a, mask, r1, rb);
+    }
+  }
+  if constexpr (2 * SP < kMaxOrder) {
+    if (mask >> (2 * SP)) {
+      RowRegs<JR, BF, SP> r2;
+      issue_rows<JR, BF, SP, 2 * SP>(a, idx, mask, r2);
+      store_rows<JR, BF, SP, 2 * SP>(a, mask, r2, rb);
+    }
+  }
+  if constexpr (3 * SP < kMaxOrder) {
+    if (mask >> (3 * SP)) {
+      RowRegs<JR, BF, SP> r3;
+      issue_rows<JR, BF, SP, 3 * SP>(a, idx, mask, r3);
+      store_rows<JR, BF, SP, 3 * SP>(a, mask, r3, rb);
     }
   }
 }
 
 // Finish the rows that straddled chunk boundaries in the previous factor
-// sub-step (mode pm): xr[bw] is the straddling row at boundary bw or -1;
-// carry slots hold [row, count, partial sum (J), old master row (J)].
-// carry_par is the LDS copy of those slots.  Fills the LDS table `split`
-// (row, then the new master row at +4) and
-// returns the number of entries.  If `store`, also writes the rows (master,
+// sub-step (mode pm).  xr[bw] is the straddling row at boundary bw or -1,
+// xn[bw] the entry number of a row's first boundary or -1 (both from the
+// schedule); cbuf holds the LDS copy of the carry slots [row, count, partial
+// sum (J), old master row (J)].  Fills the LDS table `split` (row, then the new
+// master row at +4) in row order.  If `store`, also writes the rows (master,
 // and BF16 copy in BF16 mode).
 template <int JR, bool EXACT, bool BF>
-__device__ int finish_split_rows(const ChainArgs& a, int pm, const int* xr, const float* carry_par, float* split,
-                                 int sstride, int* sfirst, int* misc, bool store) {
+__device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
+                                  const float* cbuf, float* split, int sstride, bool store) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = a.s.J[pm];
-  if (tid < 64) {  // number the first boundary of every straddling row (wave 0, ballots)
-    int ns = 0;
-    for (int b0 = 0; b0 < a.W; b0 += 64) {
-      const int bw = b0 + tid;
-      const bool first = bw >= 1 && bw < a.W && xr[bw] >= 0 && xr[bw - 1] != xr[bw];
-      const unsigned long long mask = __ballot(first);
-      const int before = __popcll(mask & ((1ull << tid) - 1ull));
-      if (bw < a.W) sfirst[bw] = first ? ns + before : -1;
-      ns += __popcll(mask);
-    }
-    if (tid == 0) misc[0] = ns;
-  }
-  __syncthreads();
-  const int nsplit = misc[0];
   for (int bw = tid + 1; bw < a.W; bw += BT) {
-    const int e = sfirst[bw];
+    const int e = xn[bw];
     if (e < 0) continue;
     const int row = xr[bw];
-    const float* slotB = carry_par + ((size_t)(bw - 1) * 2 + 1) * a.carry_stride;
+    const float* slotB = cbuf + ((size_t)(bw - 1) * 2 + 1) * a.carry_stride;
     float F[JR];
     int c = __float_as_int(slotB[1]);
 #pragma unroll
     for (int j = 0; j < JR; ++j) F[j] = (EXACT || j < pJ) ? slotB[2 + j] : 0.f;
     for (int v = bw; v < a.W && xr[v] == row; ++v) {
-      const float* slotA = carry_par + ((size_t)v * 2 + 0) * a.carry_stride;
+      const float* slotA = cbuf + ((size_t)v * 2 + 0) * a.carry_stride;
       c += __float_as_int(slotA[1]);
 #pragma unroll
       for (int j = 0; j < JR; ++j)
@@ -237,72 +274,41 @@ __device__ int finish_split_rows(const ChainArgs& a, int pm, const int* xr, cons
       if (BF) a.Ab[pm][(int64_t)row * a.Jb[pm] + j] = bf16_bits(v);
     }
   }
-  return nsplit;
 }
 
-// Per-mode tiling of the two-stage contraction.
-struct Tiling {
-  int lo, nhi, khi;       // lowest other mode, count and product of the remaining ones
-  int hi[kMaxOrder - 2];
-  int hJ[kMaxOrder - 2];  // J of each remaining mode
-  int hls[kMaxOrder - 2]; // its stride in the flat core
-  int hrs[kMaxOrder - 2]; // its offset in an LDS row buffer
-  int jlo, kp, nt;        // J_lo, J_lo padded to the MFMA K step, 16-wide j_n tiles
-  int ls_n, ls_lo, rs_lo; // core strides of j_n and j_lo, row-buffer offset of the lo row
-};
-
-__device__ __forceinline__ Tiling tiling(const Shape& s, int n, bool bf) {
-  const ModeTab t = mode_tab(s, n);
-  Tiling g;
-  g.lo = t.lo;
-  g.nhi = t.nhi;
-  g.khi = t.khi;
-#pragma unroll
-  for (int i = 0; i < kMaxOrder - 2; ++i) {
-    g.hi[i] = t.hi[i];
-    g.hJ[i] = i < t.nhi ? s.J[t.hi[i]] : 1;
-    g.hls[i] = i < t.nhi ? s.lstride[t.hi[i]] : 0;
-    g.hrs[i] = i < t.nhi ? s.rs_off[t.hi[i]] : 0;
-  }
-  g.ls_n = s.lstride[n];
-  g.ls_lo = s.lstride[t.lo];
-  g.rs_lo = s.rs_off[t.lo];
-  g.jlo = s.J[t.lo];
-  g.kp = bf ? ((g.jlo + 15) & ~15) : pad4(g.jlo);
-  g.nt = (s.J[n] + 15) / 16;
-  return g;
-}
-
-// Offsets of the remaining modes' multi-index h (mode-lowest first):
-//   hmap[h]                  = sum_i digit_i(h) * lstride[hi[i]]  (offset in the flat core)
-//   hmap[khi + h * nhi + i]  = rs_off[hi[i]] + digit_i(h)          (offset in a row buffer)
-// One thread per h, so the table and hp fills below need no division.
-__device__ __forceinline__ void build_hmap(const Tiling& g, int* hmap) {
-  for (int h = threadIdx.x; h < g.khi; h += blockDim.x) {
-    int hh = h, off = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxOrder - 2; ++i) {
-      if (i < g.nhi) {
-        const int d = hh % g.hJ[i];
-        hh /= g.hJ[i];
-        off += d * g.hls[i];
-        hmap[g.khi + h * g.nhi + i] = g.hrs[i] + d;
-      }
-    }
-    hmap[h] = off;
-  }
-}
-
-// B-operand table of mode n, built from the core Gs:
+// Tables of the two-stage contraction (B operand of stage 1), built from the
+// core Gs:
 //   FP32: TB[((h * nt + t) * kp + k) * 16 + c]   = G_(n)[16t + c, k + J_lo h]
 //   BF16: TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(same)
-// (zero outside j_n < J_n, k < J_lo).  A flat loop over table elements;
-// each thread issues its four core reads before its four table writes (the
-// two LDS arrays could alias as far as the compiler knows).
+// (zero outside j_n < J_n, k < J_lo).  With a host-built gather map (tmap[e]
+// = offset in the core or -1) the build is one load and one store per element.
 template <bool BF>
-__device__ void build_tables(const Shape& s, int n, const Tiling& g, const float* Gs, const int* hmap, float* TB) {
-  const int Jn = s.J[n];
-  const int total = g.khi * g.nt * g.kp * 16;
+__device__ __forceinline__ void build_table_map(const float* Gs, const int* tmap, int len, float* TB) {
+  unsigned short* TB16 = reinterpret_cast<unsigned short*>(TB);
+  const int BT = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < len; e0 += 4 * BT) {
+    int o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = (e0 + u * BT < len) ? tmap[e0 + u * BT] : -1;
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = o[u] >= 0 ? Gs[o[u]] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * BT;
+      if (e < len) {
+        if (BF) TB16[e] = bf16_bits(v[u]);
+        else TB[e] = v[u];
+      }
+    }
+  }
+}
+
+// The same table without a map (when the maps do not fit in LDS): index
+// arithmetic per element; hmap[h] is the core offset of multi-index h.
+template <bool BF>
+__device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const float* Gs, const int* hmap, float* TB) {
+  const int total = pt.tb_len;
   unsigned short* TB16 = reinterpret_cast<unsigned short*>(TB);
   const int BT = blockDim.x;
   for (int e0 = threadIdx.x; e0 < total; e0 += 4 * BT) {
@@ -314,20 +320,20 @@ __device__ void build_tables(const Shape& s, int n, const Tiling& g, const float
       if (e < total) {
         int k, c, ht;
         if (BF) {  // e = (ht * 16 + c) * kp + k
-          k = e % g.kp;
-          const int r = e / g.kp;
+          k = e % pt.kp;
+          const int r = e / pt.kp;
           c = r & 15;
           ht = r >> 4;
         } else {   // e = (ht * kp + k) * 16 + c
           c = e & 15;
           const int r = e >> 4;
-          k = r % g.kp;
-          ht = r / g.kp;
+          k = r % pt.kp;
+          ht = r / pt.kp;
         }
-        const int h = g.nt == 1 ? ht : ht / g.nt;
-        const int t = ht - h * g.nt;
+        const int h = pt.nt == 1 ? ht : ht / pt.nt;
+        const int t = ht - h * pt.nt;
         const int jn = 16 * t + c;
-        if (k < g.jlo && jn < Jn) v[u] = Gs[hmap[h] + k * g.ls_lo + jn * g.ls_n];
+        if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
       }
     }
 #pragma unroll
@@ -342,34 +348,36 @@ __device__ void build_tables(const Shape& s, int n, const Tiling& g, const float
 }
 
 // hp[h * chp + p] = prod over the remaining modes of the sample's rows at h
-// (1 when there are none); zero for positions p >= cnt.  Reads are batched
+// (1 when there are none); zero for positions p >= cnt.  hmap[khi + h * nhi + i]
+// is the row-buffer offset of remaining mode i at h.  Reads are batched
 // ahead of the writes, four h at a time.
-__device__ __forceinline__ void build_hp(const Shape& s, const Tiling& g, const float* rowbuf, const int* hmap,
+__device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, const float* rowbuf, const int* hmap,
                                          int cnt, int chp, float* hp) {
   const int p = threadIdx.x;
   if (p >= chp) return;
-  const float* rb = rowbuf + p * s.rs;
-  const int* ro = hmap + g.khi;
+  const int khi = pt.khi, nhi = pt.nhi;
   if (p >= cnt) {
-    for (int h = 0; h < g.khi; ++h) hp[h * chp + p] = 0.f;
+    for (int h = 0; h < khi; ++h) hp[h * chp + p] = 0.f;
     return;
   }
-  if (g.nhi == 0) {
+  if (nhi == 0) {
     hp[p] = 1.f;
     return;
   }
-  for (int h0 = 0; h0 < g.khi; h0 += 4) {
+  const float* rb = rowbuf + p * s.rs;
+  const int* ro = hmap + khi;
+  for (int h0 = 0; h0 < khi; h0 += 4) {
     float v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int h = h0 + u;
       v[u] = 1.f;
-      if (h < g.khi)
-        for (int i = 0; i < g.nhi; ++i) v[u] *= rb[ro[h * g.nhi + i]];
+      if (h < khi)
+        for (int i = 0; i < nhi; ++i) v[u] *= rb[ro[h * nhi + i]];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (h0 + u < g.khi) hp[(h0 + u) * chp + p] = v[u];
+      if (h0 + u < khi) hp[(h0 + u) * chp + p] = v[u];
   }
 }
 
@@ -377,16 +385,17 @@ __device__ __forceinline__ void build_hp(const Shape& s, const Tiling& g, const 
 // header).  Each wave carries two 16-sample tiles at once so that two
 // independent MFMA chains overlap.
 template <int JR, bool BF>
-__device__ void mfma_E(const Shape& s, int n, const Tiling& g, const float* TB, const float* rowbuf,
-                       const float* hp, int cnt, int chp, float* ebuf, int es) {
+__device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf, const float* hp,
+                       int cnt, int chp, float* ebuf, int es) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int Jn = s.J[n];
+  const int Jn = g.Jn;
   const int MT = (cnt + 15) >> 4;
   const int lo_off = g.rs_lo;
-  const int jobs = ((MT + 1) >> 1) * g.nt;  // job = (tile pair, j_n tile)
+  const int khi = g.khi, kp = g.kp, nt = g.nt, jlo = g.jlo;
+  const int jobs = ((MT + 1) >> 1) * nt;  // job = (tile pair, j_n tile)
   for (int job = wv; job < jobs; job += nwaves) {
-    const int mp = job / g.nt, t = job - mp * g.nt;
+    const int mp = job / nt, t = job - mp * nt;
     const int mt0 = 2 * mp, mt1 = 2 * mp + 1;
     const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
     f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
@@ -399,14 +408,14 @@ __device__ void mfma_E(const Shape& s, int n, const Tiling& g, const float* TB, 
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int k = 4 * ks + kq;
-        a0[ks] = (prow0 < cnt && k < g.jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f;
-        a1[ks] = (prow1 < cnt && k < g.jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f;
+        a0[ks] = (prow0 < cnt && k < jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f;
+        a1[ks] = (prow1 < cnt && k < jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f;
       }
-      const int nks = g.kp >> 2;
-      const float* tb = TB + (t * g.kp + kq) * 16 + r16;
-      const int hstride = g.nt * g.kp * 16;
+      const int nks = kp >> 2;
+      const float* tb = TB + (t * kp + kq) * 16 + r16;
+      const int hstride = nt * kp * 16;
       int h = 0;
-      for (; h + 1 < g.khi; h += 2) {  // two h per iteration: four independent MFMA chains
+      for (; h + 1 < khi; h += 2) {  // two h per iteration: four independent MFMA chains
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
         f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -441,7 +450,7 @@ __device__ void mfma_E(const Shape& s, int n, const Tiling& g, const float* TB, 
         e1[2] = fmaf(d1[2], g1.z, e1[2]);
         e1[3] = fmaf(d1[3], g1.w, e1[3]);
       }
-      for (; h < g.khi; ++h) {
+      for (; h < khi; ++h) {
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -470,14 +479,14 @@ __device__ void mfma_E(const Shape& s, int n, const Tiling& g, const float* TB, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k = 16 * ks + 4 * kq + e;
-          a0[ks][e] = (short)bf16_bits((prow0 < cnt && k < g.jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f);
-          a1[ks][e] = (short)bf16_bits((prow1 < cnt && k < g.jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f);
+          a0[ks][e] = (short)bf16_bits((prow0 < cnt && k < jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f);
+          a1[ks][e] = (short)bf16_bits((prow1 < cnt && k < jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f);
         }
       }
-      const int nks = g.kp >> 4;
-      const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * g.kp + 4 * kq;
-      const int hstride = g.nt * 16 * g.kp;
-for (int h = 0; h < g.khi; ++h) {
+      const int nks = kp >> 4;
+      const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * kp + 4 * kq;
+      const int hstride = nt * 16 * kp;
+      for (int h = 0; h < khi; ++h) {
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -515,15 +524,16 @@ for (int h = 0; h < g.khi; ++h) {
 // jobs with the same tiles and consecutive h at once, which share the A row
 // and B column loads and keep three independent MFMA chains in flight.
 template <bool BF>
-__device__ void mfma_core_grad(const Shape& s, const Tiling& g, const float* rowbuf, const float* ra, int ras,
+__device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra, int ras,
                                const float* hp, int cnt, int chp, float* out) {
   constexpr int JG = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int J0 = s.J[0];
-  const int MT0 = (J0 + 15) >> 4, NT1 = (g.jlo + 15) >> 4;
+  const int J0 = g.Jn;  // the core phase contracts with mode 0
+  const int jlo = g.jlo, khi = g.khi;
+  const int MT0 = (J0 + 15) >> 4, NT1 = (jlo + 15) >> 4;
   const int lo_off = g.rs_lo;
-  const int hgroups = (g.khi + JG - 1) / JG;
+  const int hgroups = (khi + JG - 1) / JG;
   const int jobs = hgroups * MT0 * NT1;
   constexpr int KSTEP = BF ? 16 : 4;
   const int nsteps = (cnt + KSTEP - 1) / KSTEP;
@@ -533,13 +543,13 @@ __device__ void mfma_core_grad(const Shape& s, const Tiling& g, const float* row
     const int t0 = rem / NT1, t1 = rem - t0 * NT1;
     const int j0 = 16 * t0 + r16;  // A row
     const int jl = 16 * t1 + r16;  // B column
-    const bool arow = j0 < J0, bcol = jl < g.jlo;
+    const bool arow = j0 < J0, bcol = jl < jlo;
     const int h0 = hg * JG;
     const float* hph[JG];
     bool hok[JG];
 #pragma unroll
     for (int q = 0; q < JG; ++q) {
-      hok[q] = h0 + q < g.khi;
+      hok[q] = h0 + q < khi;
       hph[q] = hp + (hok[q] ? h0 + q : h0) * chp;
     }
     f32x4 c[JG];
@@ -596,9 +606,27 @@ __device__ void mfma_core_grad(const Shape& s, const Tiling& g, const float* row
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int jr = 16 * t0 + 4 * kq + i;
-        if (jr < J0 && bcol) out[jr + J0 * (jl + g.jlo * (h0 + q))] = c[q][i];
+        if (jr < J0 && bcol) out[jr + J0 * (jl + jlo * (h0 + q))] = c[q][i];
       }
     }
+  }
+}
+
+// Copy the carry slots of parity `par` into LDS (all loads issued before the
+// stores when they fit four vectors per thread).
+__device__ __forceinline__ void copy_carry(const ChainArgs& a, int par, float* cbuf) {
+  const int tot = (int)(((size_t)a.W * 2 * a.carry_stride) >> 2);
+  const f32x4* src = reinterpret_cast<const f32x4*>(a.carry + (size_t)par * a.W * 2 * a.carry_stride);
+  f32x4* dst = reinterpret_cast<f32x4*>(cbuf);
+  const int BT = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * BT) {
+    f32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * BT < tot) v[u] = src[i0 + u * BT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * BT < tot) dst[i0 + u * BT] = v[u];
   }
 }
 
@@ -619,7 +647,8 @@ __device__ void mfma_core_grad(const Shape& s, const Tiling& g, const float* row
 //   of the next sub-step from the chunks' carried partial sums and the
 //   carried old row (every workgroup computes it identically into an LDS
 //   table; workgroup 0 stores it; until the next barrier nobody else reads it
-//   from global memory).
+//   from global memory, and the rows of that mode are read after the barrier
+//   that follows).
 // Carry slot: [0] row, [1] count, [2, 2+J) partial sum, [2+J, 2+2J) old row.
 // ---------------------------------------------------------------------------
 template <int JU, int BFI>
@@ -627,6 +656,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   constexpr int JR = JU ? JU : kMaxRank;
   constexpr bool EXACT = JU != 0;
   constexpr bool BF = BFI != 0;
+  constexpr int CV = RowRegs<JR, BF, 1>::C;
+  // modes whose rows are parked in registers between sub-steps (generic ranks: none)
+  constexpr int NPF = EXACT ? ((12 / CV) < kMaxOrder ? (12 / CV) : kMaxOrder) : 0;
   extern __shared__ float lds[];
   const Shape& s = a.s;
   const int N = s.N;
@@ -646,34 +678,48 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   float* ebuf = lds + L.ebuf;
   float* rabuf = lds + L.ra;
   float* split = lds + L.split;
-  float* cbuf = lds + L.cbuf;  // the previous phase's carry slots, copied at phase start
+  float* cbuf = lds + L.cbuf;
   int* hmap = reinterpret_cast<int*>(lds + L.hmap);
+  int* tmap = reinterpret_cast<int*>(lds + L.tmap);
   float* wscr = lds + L.wscr;
   int* ints = reinterpret_cast<int*>(lds + L.ints);
-  int* rowids = ints;                // BT
-  int* segmax = rowids + BT;         // BT / 64
-  int* xa = segmax + (BT >> 6);      // W   crossing rows, buffers rotated per phase
-  int* xb = xa + a.W;                // W
-  int* sfirst = xb + a.W;            // W
-  int* misc = sfirst + a.W;          // 8
+  int* xa = ints;            // W  straddling rows of the previous sub-step's boundaries
+  int* xn = xa + a.W;        // W  their entry numbers
+  int* misc = xn + a.W;      // 8
   const int chp = L.chp, es = L.es, ras = L.ras, sstride = L.sstride, wstride = L.wstride;
+  const unsigned allm = (1u << N) - 1u;
+  const unsigned npfm = (1u << NPF) - 1u;
+  const int XS = xrow_stride(a.W);
+  const size_t carry_par_stride = (size_t)a.W * 2 * a.carry_stride;
+  const int64_t T = a.T, M = a.M;
 
+  // ---- set-up: core, index maps, resident tables
   for (int lin = tid; lin < P; lin += BT) Gs[lin] = a.G[lin];
+  for (int i = tid; i < L.aux_len; i += BT) {
+    const int v = a.aux[i];
+    if (i < L.hm_len) hmap[i] = v;
+    else tmap[i - L.hm_len] = v;
+  }
   __syncthreads();
+  if (L.tb_all) {
+    for (int n = 0; n < N; ++n) {
+      const PhaseTab& q = a.pt[n + 1];
+      build_table_map<BF>(Gs, tmap + q.tb_off, q.tb_len, BF ? TB + (q.tb_off >> 1) : TB + q.tb_off);
+    }
+  }
 
   unsigned passed = 0;
-  int pm = -1;   // mode of the previous phase (-1: core sub-step or none)
   int ppar = 0;  // carry parity written by the previous phase
   int par = 0;   // carry parity of the current phase
-  int* xprev = xa;
-  int* xcur = xb;
-  const int64_t T = a.T, M = a.M;
-  const size_t carry_par_stride = (size_t)a.W * 2 * a.carry_stride;
+  bool first = true;
 
-  uint32_t rec[kMaxOrder + 1];
+  LaneRec cur;
+  if (a.b_begin < a.b_end) load_lane_rec(a, a.b_begin, 0, cur);
+  else cur.valid = false;
+  RowRegs<JR, BF, NPF> pf;   // next phase's rows, loaded during this phase
+  float an_cur[JR], an_nxt[JR];  // BF16 mode: FP32 master row of the lane's own-mode row
 #pragma unroll
-  for (int i = 0; i < kMaxOrder + 1; ++i) rec[i] = 0;
-  if (a.b_begin < a.b_end) load_phase_record(a, a.b_begin, 0, rec);
+  for (int j = 0; j < JR; ++j) an_cur[j] = an_nxt[j] = 0.f;
 
   for (int64_t b = a.b_begin; b < a.b_end; ++b) {
     const int64_t base = b * M;
@@ -682,70 +728,107 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     const int cnt = max(0, min(a.chunk, m - lo));
 
     for (int ph = 0; ph <= N; ++ph) {
-      const int n = ph == 0 ? 0 : ph - 1;  // the mode whose unfolding this phase contracts with
-      const int Jn = EXACT ? JR : s.J[n];
+      const PhaseTab& pt = a.pt[ph];
+      const int n = pt.n;
+      const int Jn = EXACT ? JR : pt.Jn;
+      const int pm = first ? -1 : pt.pm;
       const bool active = tid < cnt;
-      const Tiling g = tiling(s, n, BF);
-
-      // ---- 1. this lane's sample: record and rows (issued first: longest latency)
-      int idx[kMaxOrder];
-#pragma unroll
-      for (int k = 0; k < kMaxOrder; ++k) idx[k] = (k < N) ? (int)rec[k] : 0;
-      const float x = __uint_as_float(pick(rec, s.R - 1));
+      const bool splits = pm >= 0 && a.W > 1;
       float* rb = rowbuf + tid * s.rs;
-      if (active) gather_sample_rows<JR, BF>(a, idx, rb);
-      float an[JR];  // own-mode FP32 master row (the row the update starts from)
+
+      // ---- 1. after the barrier, one batch of loads: the rows of the modes
+      //      the two previous phases updated, the carry slots and boundary
+      //      rows of the previous phase, the first core partials
+      const int P4 = Pp >> 2;
+      const f32x4* psrc = reinterpret_cast<const f32x4*>(a.partial);
+      f32x4 pp[8];  // core phase 1: the first 8 workgroups' partials of column tid
+      {
+        const unsigned post = first ? allm : (((unsigned)pt.post | (allm & ~npfm)) & allm);
+        const int64_t bp = ph == 0 ? b - 1 : b;
+        const int* xsrc = a.xrow + ((size_t)(splits ? bp : 0) * N + (splits ? pm : 0)) * XS;
+        const int ctot = (int)(carry_par_stride >> 2);
+        const f32x4* csrc = reinterpret_cast<const f32x4*>(a.carry + (size_t)ppar * carry_par_stride);
+        f32x4 cv[4];
+        int xv = -1, xnv = -1, xc = 0;
+        if (splits) {
 #pragma unroll
-      for (int j = 0; j < JR; ++j) an[j] = 0.f;
-      if (BF && active && ph > 0) {
-        const float* src = a.A[n] + (int64_t)pick(idx, n) * s.Jp[n];
+          for (int u = 0; u < 4; ++u)
+            if (tid + u * BT < ctot) cv[u] = csrc[tid + u * BT];
+          if (tid < a.W) {
+            xv = xsrc[tid];
+            xnv = xsrc[a.W + tid];
+          }
+          if (tid == 0) xc = xsrc[2 * a.W];
+        }
+        if (ph == 1 && tid < P4) {
 #pragma unroll
-        for (int j = 0; j < JR; ++j)
-          if (EXACT || j < Jn) an[j] = src[j];
+          for (int v = 0; v < 8; ++v)
+            if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
+        }
+        if (active) gather_rows<JR, BF>(a, cur.idx, post, rb);
+        if (splits) {
+          f32x4* cdst = reinterpret_cast<f32x4*>(cbuf);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (tid + u * BT < ctot) cdst[tid + u * BT] = cv[u];
+          for (int i = tid + 4 * BT; i < ctot; i += BT) cdst[i] = csrc[i];
+          for (int bw = tid; bw < a.W; bw += BT) {
+            xa[bw] = bw == tid ? xv : xsrc[bw];
+            xn[bw] = bw == tid ? xnv : xsrc[a.W + bw];
+          }
+          if (tid == 0) misc[0] = xc;
+        }
       }
-      if (ph > 0 && a.W > 1)
-        for (int bw = tid; bw < a.W; bw += BT) xcur[bw] = a.xrow[((size_t)b * N + n) * a.W + bw];
-      if (pm >= 0 && a.W > 1) {
-        const float4* src = reinterpret_cast<const float4*>(a.carry + (size_t)ppar * carry_par_stride);
-        float4* dst = reinterpret_cast<float4*>(cbuf);
-        for (int i = tid; i < (int)(carry_par_stride >> 2); i += BT) dst[i] = src[i];
+      // the next phase's record (read-only; its latency overlaps this phase)
+      int nph = ph + 1;
+      int64_t nbb = b;
+      if (nph > N) {
+        nph = 0;
+        ++nbb;
       }
+      const bool has_next = nbb < a.b_end;
+      LaneRec nx;
+      if (has_next) load_lane_rec(a, nbb, nph, nx);
+      else nx.valid = false;
+      __syncthreads();
 
       // ---- 2. core: finish the core step of this minibatch (same in every workgroup)
       if (ph == 1) {
         const float inv_m = 1.0f / (float)m;
-        const int P4 = Pp >> 2;
-        const float4* src = reinterpret_cast<const float4*>(a.partial);
         for (int l4 = tid; l4 < P4; l4 += BT) {
-          float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 16
-          for (int v = 0; v < a.W; ++v) {
-            const float4 t4 = src[(size_t)v * P4 + l4];
-            sum.x += t4.x;
-            sum.y += t4.y;
-            sum.z += t4.z;
-            sum.w += t4.w;
+          f32x4 sum = {0.f, 0.f, 0.f, 0.f};
+          int v0 = 0;
+          if (l4 == tid) {  // the loads issued with the batch
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+              if (v < a.W) sum += pp[v];
+            v0 = 8;
           }
-          const float sv[4] = {sum.x, sum.y, sum.z, sum.w};
+#pragma unroll 16
+          for (int v = v0; v < a.W; ++v) sum += psrc[(size_t)v * P4 + l4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int lin = 4 * l4 + i;
             if (lin < P) {
               const float gv = Gs[lin];
-              Gs[lin] = gv - a.gG * (-sv[i] * inv_m + a.lG * gv);
+              Gs[lin] = gv - a.gG * (-sum[i] * inv_m + a.lG * gv);
             }
           }
         }
         __syncthreads();
+        if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
+          build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
       }
+      if (!L.tb_all) build_table_arith<BF>(pt, Gs, hmap + pt.hm_off, TB);
 
       // ---- 3. rows of the previous factor sub-step that straddled chunks
-      if (pm >= 0 && a.W > 1) {
-        const int nsplit = finish_split_rows<JR, EXACT, BF>(a, pm, xprev, cbuf, split, sstride, sfirst, misc, w == 0);
+      if (splits) {
+        const int nsplit = misc[0];
+        finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
         if (active && nsplit > 0) {
           // the table follows the chunk boundaries, so its rows are increasing
           const int pJ = s.J[pm];
-          const int prow = pick(idx, pm);
+          const int prow = cur.rpm;
           int lo2 = 0, hi2 = nsplit;
           while (lo2 < hi2) {
             const int mid = (lo2 + hi2) >> 1;
@@ -753,31 +836,32 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
             else hi2 = mid;
           }
           if (lo2 < nsplit && __float_as_int(split[lo2 * sstride]) == prow) {
+            float* dst = rb + s.rs_off[pm];
             for (int j = 0; j < pJ; ++j) {
               const float v = split[lo2 * sstride + 4 + j];
-              rb[s.rs_off[pm] + j] = BF ? bf16_round(v) : v;
+              dst[j] = BF ? bf16_round(v) : v;
             }
           }
         }
       }
-      // own-mode master row in FP32 mode is the gathered row
-      __syncthreads();
-      // ---- 4. contraction tables of this phase's mode, E_p for every sample
-      build_hmap(g, hmap);
-      __syncthreads();
-      build_tables<BF>(s, n, g, Gs, hmap, TB);
-      build_hp(s, g, rowbuf, hmap, cnt, chp, hp);
-      __syncthreads();
-      mfma_E<JR, BF>(s, n, g, TB, rowbuf, hp, cnt, chp, ebuf, es);
-      {  // the next phase's record (read-only; its load overlaps the rest of this phase)
-        int64_t nbb = b;
-        int nph = ph + 1;
-        if (nph > N) {
-          nph = 0;
-          ++nbb;
-        }
-        if (nbb < a.b_end) load_phase_record(a, nbb, nph, rec);
+
+      // ---- 4. the next phase's rows that no phase writes before it: into registers
+      unsigned pre = 0;
+      if (has_next) pre = (allm & ~(unsigned)a.pt[nph].post) & npfm;
+      if (NPF > 0 && nx.valid && pre) issue_rows<JR, BF, NPF, 0>(a, nx.idx, pre, pf);
+      if (BF && has_next && nx.valid && nph > 0) {
+        const float* src = a.A[a.pt[nph].n] + (int64_t)nx.rown * s.Jp[a.pt[nph].n];
+        const int Jx = a.pt[nph].Jn;
+#pragma unroll
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < Jx) an_nxt[j] = src[j];
       }
+
+      // ---- 5. E_p for every sample of the chunk
+      build_hp(s, pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
+      __syncthreads();
+      const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
+      mfma_E<JR, BF>(s, pt, TBn, rowbuf, hp, cnt, chp, ebuf, es);
       __syncthreads();
 
       if (ph == 0) {
@@ -788,52 +872,43 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
             float xh = 0.f;
 #pragma unroll
             for (int j = 0; j < JR; ++j)
-              if (EXACT || j < Jn) xh = fmaf(rb[s.rs_off[0] + j], ebuf[tid * es + j], xh);
-            r = x - xh;
+              if (EXACT || j < Jn) xh = fmaf(rb[j], ebuf[tid * es + j], xh);  // mode 0's row sits at offset 0
+            r = cur.x - xh;
           }
 #pragma unroll
           for (int j = 0; j < JR; ++j)
-            if (EXACT || j < Jn) rabuf[tid * ras + j] = active ? r * rb[s.rs_off[0] + j] : 0.f;
+            if (EXACT || j < Jn) rabuf[tid * ras + j] = active ? r * rb[j] : 0.f;
         }
-        // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
-        const Tiling g0 = tiling(s, 0, BF);
         __syncthreads();
-        mfma_core_grad<BF>(s, g0, rowbuf, rabuf, ras, hp, cnt, chp, a.partial + (size_t)w * Pp);
+        // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
+        mfma_core_grad<BF>(s, pt, rowbuf, rabuf, ras, hp, cnt, chp, a.partial + (size_t)w * Pp);
       } else {
         // ================= mode-n sub-step =================
-        float u[JR];
+        float u[JR], an[JR];
 #pragma unroll
-        for (int j = 0; j < JR; ++j) u[j] = 0.f;
-        const int row = active ? pick(idx, n) : -1;
+        for (int j = 0; j < JR; ++j) u[j] = an[j] = 0.f;
+        const int rsn = pt.rs_n;
         if (active) {
           float xh = 0.f;
 #pragma unroll
           for (int j = 0; j < JR; ++j) {
             if (EXACT || j < Jn) {
               const float e = ebuf[tid * es + j];
-              if (!BF) an[j] = rb[s.rs_off[n] + j];
-              xh = fmaf(rb[s.rs_off[n] + j], e, xh);
+              const float av = rb[rsn + j];
+              an[j] = BF ? an_cur[j] : av;
+              xh = fmaf(av, e, xh);
               u[j] = e;
             }
           }
-          const float r = x - xh;
+          const float r = cur.x - xh;
 #pragma unroll
           for (int j = 0; j < JR; ++j)
             if (EXACT || j < Jn) u[j] = -r * u[j];
-          rowids[tid] = row;
         }
-        __syncthreads();
-        // chunk-local segment heads; sf = first chunk position of my row's run
-        const bool head = active && (tid == 0 || rowids[tid - 1] != row);
-        int sf = head ? tid : 0;
-        for (int d = 1; d < 64; d <<= 1) {
-          const int o = __shfl_up(sf, d);
-          if (lane >= d) sf = max(sf, o);
-        }
-        if (lane == 63) segmax[wv] = sf;
-        __syncthreads();
-        for (int v = 0; v < wv; ++v) sf = max(sf, segmax[v]);
-        // wave-level segmented inclusive scan of u (Hillis-Steele, fixed order)
+        // wave-level segmented inclusive scan of u (Hillis-Steele, fixed order);
+        // sf = first chunk position of my row's run (from the schedule)
+        const int meta = cur.meta;
+        const int sf = meta & 511;
         const int wstart = max(sf, wv * 64) - wv * 64;
         for (int d = 1; d < 64; d <<= 1) {
           const bool take = (lane - d) >= wstart;
@@ -857,11 +932,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           for (int j = 0; j < JR; ++j)
             if (EXACT || j < Jn) u[j] += wscr[v * wstride + j];
         }
-        const bool tail = active && (tid == cnt - 1 || rowids[tid + 1] != row);
-        if (tail) {
+        if (active && (meta & kMetaTail)) {
+          const int row = cur.rown;
           const int c = tid - sf + 1;
-          const bool before = (sf == 0) && a.W > 1 && xcur[w] >= 0;                          // run began earlier
-          const bool after = (tid == cnt - 1) && a.W > 1 && w + 1 < a.W && xcur[w + 1] >= 0;  // run goes on
+          const bool before = (meta & kMetaBefore) != 0;  // run began in an earlier chunk
+          const bool after = (meta & kMetaAfter) != 0;    // run goes on in the next chunk
           if (!before && !after) {
             float* arow = a.A[n] + (int64_t)row * s.Jp[n];
             unsigned short* brow = BF ? a.Ab[n] + (int64_t)row * a.Jb[n] : nullptr;
@@ -888,71 +963,183 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           }
         }
       }
-      // ---- 5. barrier: the next sub-step needs this one's result
+      // ---- 6. barrier: the next sub-step needs this one's result.  Between
+      //      arrival and wait: park the prefetched rows, build the tables the
+      //      core update changed (neither reads what other workgroups write).
       passed += 1;
       barrier_arrive(a, passed);
+      if (NPF > 0 && nx.valid && pre) store_rows<JR, BF, NPF, 0>(a, pre, pf, rb);
+      if (ph == 1 && L.tb_all) {
+        for (int n2 = 1; n2 < N; ++n2) {
+          const PhaseTab& q = a.pt[n2 + 1];
+          build_table_map<BF>(Gs, tmap + q.tb_off, q.tb_len, BF ? TB + (q.tb_off >> 1) : TB + q.tb_off);
+        }
+      }
       if (!barrier_wait(a, passed, misc + 7)) return;
-      pm = ph - 1;  // -1 after the core sub-step
+      first = false;
+      cur = nx;
+#pragma unroll
+      for (int j = 0; j < JR; ++j) an_cur[j] = an_nxt[j];
       ppar = par;
       par ^= 1;
-      int* tmp = xprev;
-      xprev = xcur;
-      xcur = tmp;
     }
   }
   // ---- flush: rows of the last factor sub-step that straddled chunks
-  if (pm >= 0 && a.W > 1 && w == 0) {
-    const float4* src = reinterpret_cast<const float4*>(a.carry + (size_t)ppar * carry_par_stride);
-    float4* dst = reinterpret_cast<float4*>(cbuf);
-    for (int i = tid; i < (int)(carry_par_stride >> 2); i += BT) dst[i] = src[i];
+  if (!first && a.W > 1 && w == 0) {
+    const int pm = N - 1;
+    const int* xsrc = a.xrow + ((size_t)(a.b_end - 1) * N + pm) * XS;
+    for (int bw = tid; bw < a.W; bw += BT) {
+      xa[bw] = xsrc[bw];
+      xn[bw] = xsrc[a.W + bw];
+    }
+    if (tid == 0) misc[0] = xsrc[2 * a.W];
+    copy_carry(a, ppar, cbuf);
     __syncthreads();
-    finish_split_rows<JR, EXACT, BF>(a, pm, xprev, cbuf, split, sstride, sfirst, misc, true);
+    finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true);
   }
   if (w == 0)
     for (int lin = tid; lin < P; lin += BT) a.G[lin] = Gs[lin];
 }
 
-// LDS plan of the chain (floats; every region starts on 16 bytes).
-size_t plan_chain_lds(ChainArgs& a, int threads, bool bf) {
+// ---------------------------------------------------------------------------
+// Host side: the LDS plan, the per-phase constants and the index maps.
+// ---------------------------------------------------------------------------
+size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   const Shape& s = a.s;
   // every region below is sized from these: refuse an incomplete request
   if (a.W < 1 || a.chunk < 1 || a.chunk > threads || (a.W > 1 && (a.carry_stride < 4 || a.split_cap < a.W - 1)))
     return 0;
+  if (s.N < 2 || s.N > kMaxOrder) return 0;
+  const int N = s.N;
   const int JU = chain_variant(s);
   const int JR = JU ? JU : kMaxRank;
   auto al = [](size_t f) { return (f + 3) & ~(size_t)3; };
-  ChainLayout& L = a.lay;
-  int jmax = 0;
-  size_t tb = 0, khimax = 1;
-  for (int n = 0; n < s.N; ++n) {
+  struct ModeT {
+    int lo, nhi, khi, jlo, kp, nt, hi[kMaxOrder];
+    int hm_off, tb_off, tb_len;
+  } mt[kMaxOrder];
+  int jmax = 0, hm_len = 0, tb_sum = 0, tb_max = 0, khimax = 1;
+  for (int n = 0; n < N; ++n) {
+    ModeT& q = mt[n];
     jmax = s.J[n] > jmax ? s.J[n] : jmax;
-    const int lo = n == 0 ? 1 : 0;
-    const int jlo = s.J[lo];
-    const size_t khi = (size_t)s.P / s.J[n] / jlo;
-    const int nt = (s.J[n] + 15) / 16;
-    const size_t kp = bf ? (size_t)((jlo + 15) & ~15) : (size_t)pad4(jlo);
-    const size_t f = bf ? (khi * nt * 16 * kp + 1) / 2 : khi * nt * kp * 16;
-    tb = f > tb ? f : tb;
-    khimax = khi > khimax ? khi : khimax;
+    q.lo = n == 0 ? 1 : 0;
+    q.nhi = 0;
+    q.khi = 1;
+    for (int k = 0; k < N; ++k)
+      if (k != n && k != q.lo) {
+        q.hi[q.nhi++] = k;
+        q.khi *= s.J[k];
+      }
+    q.jlo = s.J[q.lo];
+    q.kp = bf ? ((q.jlo + 15) & ~15) : pad4(q.jlo);
+    q.nt = (s.J[n] + 15) / 16;
+    q.tb_len = q.khi * q.nt * q.kp * 16;
+    q.hm_off = hm_len;
+    hm_len += q.khi * (1 + q.nhi);
+    q.tb_off = tb_sum;
+    tb_sum += q.tb_len;
+    tb_max = q.tb_len > tb_max ? q.tb_len : tb_max;
+    khimax = q.khi > khimax ? q.khi : khimax;
   }
+  auto tbf = [&](int len) { return bf ? (size_t)(len + 1) / 2 : (size_t)len; };
+  ChainLayout& L = a.lay;
   L.chp = (a.chunk + 15) & ~15;
   L.es = 16 * ((jmax + 15) / 16) + 1;
   L.ras = pad4(JR) + 1;
   L.sstride = 4 + pad4(JR);
   L.wstride = pad4(JR) + 4;
+  size_t common = al(s.P) + al((size_t)L.chp * s.rs) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
+                  al((size_t)L.chp * L.ras) + al((size_t)a.split_cap * L.sstride) +
+                  al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0) + al((size_t)hm_len) +
+                  al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
+  const size_t all_resident = common + al(tbf(tb_sum)) + al((size_t)tb_sum);
+  L.tb_all = all_resident * 4 <= 163840 ? 1 : 0;
   size_t off = 0;
   L.gs = (int)off;    off += al(s.P);
-  L.tb = (int)off;    off += al(tb);
-  L.row = (int)off;   off += al((size_t)threads * s.rs);
-  L.hp = (int)off;    off += al(khimax * L.chp);
+  L.tb = (int)off;    off += al(L.tb_all ? tbf(tb_sum) : tbf(tb_max));
+  L.row = (int)off;   off += al((size_t)L.chp * s.rs);
+  L.hp = (int)off;    off += al((size_t)khimax * L.chp);
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras);
   L.split = (int)off; off += al((size_t)a.split_cap * L.sstride);
   L.cbuf = (int)off;  off += al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0);
-  L.hmap = (int)off;  off += al(khimax * (size_t)(s.N > 2 ? s.N - 1 : 1));
+  L.hmap = (int)off;  off += al((size_t)hm_len);
+  L.tmap = (int)off;  off += L.tb_all ? al((size_t)tb_sum) : 0;
   L.wscr = (int)off;  off += al((size_t)(threads / 64) * L.wstride);
-  L.ints = (int)off;  off += threads + threads / 64 + 3 * a.W + 8;
+  L.ints = (int)off;  off += 2 * (size_t)a.W + 8;
   L.total = (int)off;
+  L.aux_len = hm_len + (L.tb_all ? tb_sum : 0);
+  L.hm_len = hm_len;
+
+  // per-phase constants
+  auto upd_of = [&](int ph) { return ph == 0 ? -1 : ph - 1; };
+  for (int ph = 0; ph <= N; ++ph) {
+    PhaseTab& t = a.pt[ph];
+    const int n = ph == 0 ? 0 : ph - 1;
+    const ModeT& q = mt[n];
+    t.n = n;
+    t.upd = upd_of(ph);
+    t.pm = upd_of((ph + N) % (N + 1));
+    const int pm2 = upd_of((ph + N - 1) % (N + 1));
+    t.post = (t.pm >= 0 ? 1 << t.pm : 0) | (pm2 >= 0 ? 1 << pm2 : 0);
+    t.khi = q.khi;
+    t.nhi = q.nhi;
+    t.jlo = q.jlo;
+    t.kp = q.kp;
+    t.nt = q.nt;
+    t.ls_n = s.lstride[n];
+    t.ls_lo = s.lstride[q.lo];
+    t.rs_lo = s.rs_off[q.lo];
+    t.rs_n = s.rs_off[n];
+    t.Jn = s.J[n];
+    t.tb_off = L.tb_all ? q.tb_off : 0;
+    t.tb_len = q.tb_len;
+    t.hm_off = q.hm_off;
+    t.tm_off = t.tb_off;
+  }
+  for (int ph = N + 1; ph <= kMaxOrder; ++ph) a.pt[ph] = PhaseTab{};
+
+  // index maps: per mode, [khi core offsets][khi * nhi row-buffer offsets],
+  // then (resident tables) the table gather maps in table layout
+  if (aux) {
+    for (int n = 0; n < N; ++n) {
+      const ModeT& q = mt[n];
+      int* hm = aux + q.hm_off;
+      std::vector<int> hoff(q.khi);
+      for (int h = 0; h < q.khi; ++h) {
+        int hh = h, o = 0;
+        for (int i = 0; i < q.nhi; ++i) {
+          const int Jk = s.J[q.hi[i]];
+          const int d = hh % Jk;
+          hh /= Jk;
+          o += d * s.lstride[q.hi[i]];
+          hm[q.khi + h * q.nhi + i] = s.rs_off[q.hi[i]] + d;
+        }
+        hm[h] = o;
+        hoff[h] = o;
+      }
+      if (L.tb_all) {
+        int* tm = aux + hm_len + q.tb_off;
+        for (int e = 0; e < q.tb_len; ++e) {
+          int k, c, ht;
+          if (bf) {
+            k = e % q.kp;
+            const int r = e / q.kp;
+            c = r & 15;
+            ht = r >> 4;
+          } else {
+            c = e & 15;
+            const int r = e >> 4;
+            k = r % q.kp;
+            ht = r / q.kp;
+          }
+          const int h = ht / q.nt, t = ht - h * q.nt;
+          const int jn = 16 * t + c;
+          tm[e] = (k < q.jlo && jn < s.J[n]) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
+        }
+      }
+    }
+  }
   return off * 4;
 }
 
@@ -963,7 +1150,10 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
   const size_t bytes = (size_t)a.lay.total * 4;
   {  // the plan must be the one these arguments produce
     ChainArgs chk = a;
-    if (plan_chain_lds(chk, threads, a.bf16 != 0) != bytes || chk.lay.cbuf != a.lay.cbuf || chk.lay.ints != a.lay.ints)
+    if (plan_chain_lds(chk, threads, a.bf16 != 0) != bytes || chk.lay.cbuf != a.lay.cbuf ||
+        chk.lay.ints != a.lay.ints || chk.lay.tmap != a.lay.tmap || chk.lay.aux_len != a.lay.aux_len ||
+        chk.lay.hm_len != a.lay.hm_len ||
+        !a.aux)
       return hipErrorInvalidValue;
   }
   hipError_t e = hipSuccess;

@@ -31,13 +31,43 @@ struct Shape {
 
 // LDS regions of a chain workgroup (float offsets) and strides.
 struct ChainLayout {
-  int gs, tb, row, hp, ebuf, ra, split, cbuf, hmap, wscr, ints, total;
+  int gs, tb, row, hp, ebuf, ra, split, cbuf, hmap, tmap, wscr, ints, total;
   int chp;      // chunk rounded up to 16 (MFMA tile rows)
   int es;       // stride of the E buffer (odd)
   int ras;      // stride of the r * a(0) buffer
   int sstride;  // stride of the split-row table
   int wstride;  // stride of the per-wave scan tails
+  int tb_all;   // 1: the tables of every mode stay resident (rebuilt once per minibatch)
+  int aux_len;  // ints of the host-built index maps (row-offset maps, then table gather maps)
+  int hm_len;   // ints of the row-offset maps (the first part of aux)
 };
+
+// Per-phase constants of the chain, built on the host.  Phase 0 is the core
+// sub-step, phase ph >= 1 the sub-step of mode ph - 1.
+struct PhaseTab {
+  int n;         // mode whose unfolding the phase contracts with (0 for the core phase)
+  int upd;       // mode the phase updates (-1: core phase)
+  int pm;        // mode the previous phase updated (-1: none): its straddling rows are finished now
+  int post;      // bit mask of modes whose rows are read after the barrier (updated by the two previous phases)
+  int khi, nhi;  // product and count of the modes other than n and lo
+  int jlo, kp, nt;
+  int ls_n, ls_lo, rs_lo, rs_n, Jn;
+  int tb_off;    // element offset of mode n's table in the table region
+  int tb_len;    // elements of mode n's table
+  int hm_off;    // int offset of mode n's row-offset map
+  int tm_off;    // int offset of mode n's table gather map (resident tables only)
+};
+
+// Schedule words per (minibatch, mode) in the chunk-boundary array:
+// [0, W) straddling row or -1, [W, 2W) entry number of a straddling row's
+// first boundary or -1, [2W] number of straddling rows.
+__host__ __device__ inline int xrow_stride(int W) { return 2 * W + 4; }
+
+// Run metadata of a sorted position (16 bits): bits 0-8 the chunk-local
+// position where its row's run starts in the chunk, bit 9 last position of
+// the run in the chunk, bit 10 run began in an earlier chunk, bit 11 run goes
+// on in the next chunk.
+constexpr int kMetaTail = 1 << 9, kMetaBefore = 1 << 10, kMetaAfter = 1 << 11;
 
 // Arguments of the persistent minibatch chain kernel.
 struct ChainArgs {
@@ -45,7 +75,9 @@ struct ChainArgs {
   const uint32_t* coo;      // records in epoch order (T x R words)
   const uint16_t* sigma;    // [N][T] per-minibatch sorted positions
   const uint32_t* rec_sorted; // [N][T] records in (row, position) order per minibatch
-  const int* xrow;          // [nb][N][W] row straddling each chunk boundary, or -1
+  const int* xrow;          // [nb][N][xrow_stride(W)] chunk-boundary rows and their numbering
+  const uint16_t* meta;     // [N][T] run metadata of each sorted position
+  const int* aux;           // host-built maps (lay.aux_len ints)
   float* A[kMaxOrder];      // FP32 master factors, I_n x Jp_n
   uint16_t* Ab[kMaxOrder];  // BF16 read copies (null in FP32 mode), I_n x Jb_n
   int Jb[kMaxOrder];        // row stride of the BF16 copies (J_n rounded up to 8)
@@ -64,6 +96,7 @@ struct ChainArgs {
   long long spin_limit;     // barrier give-up bound (iterations)
   int split_cap;            // entries of the LDS split-row table
   ChainLayout lay;          // filled by plan_chain_lds
+  PhaseTab pt[kMaxOrder + 1];
 };
 
 // Which J specialisation of the chain serves a shape: the common rank when
@@ -75,12 +108,14 @@ hipError_t launch_perm_gather(const Shape& s, const uint32_t* coo, uint32_t* coo
                               uint64_t seed, int64_t epoch, hipStream_t st);
 hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, hipStream_t st);
 hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg,
-                       uint32_t* rec_sorted, int W, int chunk, int64_t T, int64_t M, int64_t b_begin, int64_t b_end,
-                       hipStream_t st);
+                       uint32_t* rec_sorted, uint16_t* meta, int W, int chunk, int64_t T, int64_t M,
+                       int64_t b_begin, int64_t b_end, hipStream_t st);
 hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const uint16_t* sigma,
                                  int64_t T, int64_t M, int64_t b, int mode, int32_t* seg_off,
                                  int32_t* seg_row, int32_t* nseg, hipStream_t st);
-size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16);
+// Fills a.lay and a.pt and the index maps (aux, a.lay.aux_len ints); returns
+// the LDS bytes of one workgroup, or 0 if the request is inconsistent.
+size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
 size_t chain_lds_bytes(const ChainArgs& a, int threads);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,

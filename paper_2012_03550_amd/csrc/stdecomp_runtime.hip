@@ -31,6 +31,8 @@ struct stdecomp_handle {
   int W = 1, chunk = 1, threads = 64, split_cap = 0, carry_stride = 0;
   size_t chain_lds = 0;
   stdk::ChainLayout lay{};
+  stdk::PhaseTab pt[kMaxOrder + 1] = {};
+  std::vector<int> aux_host;  // index maps of the chain (uploaded to aux)
   // device buffers
   uint32_t* coo = nullptr;
   uint32_t* coo_perm = nullptr;
@@ -38,6 +40,8 @@ struct stdecomp_handle {
   uint32_t* rec_sorted = nullptr;
   int* xrow = nullptr;
   int* nseg = nullptr;
+  uint16_t* meta = nullptr;
+  int* aux = nullptr;
   float* A[kMaxOrder] = {};
   uint16_t* Ab[kMaxOrder] = {};  // BF16 read copies (BF16 mode)
   int Jb[kMaxOrder] = {};
@@ -148,7 +152,11 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
   a.carry_stride = h->carry_stride;
   h->chain_lds = stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16);
   if (h->chain_lds == 0) return fail(h, STD_E_INVAL, "inconsistent chain plan");
+  h->aux_host.assign((size_t)(a.lay.aux_len > 0 ? a.lay.aux_len : 1), 0);
+  if (stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16, h->aux_host.data()) != h->chain_lds)
+    return fail(h, STD_E_INVAL, "inconsistent chain plan");
   h->lay = a.lay;
+  for (int i = 0; i <= kMaxOrder; ++i) h->pt[i] = a.pt[i];
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
     return fail(h, STD_E_DEVICE, "hipGetDeviceProperties failed");
@@ -167,6 +175,8 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.sigma = h->sigma;
   a.rec_sorted = h->rec_sorted;
   a.xrow = h->xrow;
+  a.meta = h->meta;
+  a.aux = h->aux;
   for (int n = 0; n < h->s.N; ++n) {
     a.A[n] = h->A[n];
     a.Ab[n] = h->Ab[n];
@@ -174,6 +184,7 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   }
   a.bf16 = h->dtype == STD_DTYPE_BF16 ? 1 : 0;
   a.lay = h->lay;
+  for (int i = 0; i <= kMaxOrder; ++i) a.pt[i] = h->pt[i];
   a.G = h->G;
   a.partial = h->partial;
   a.carry = h->carry;
@@ -195,7 +206,7 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
 
 int run_schedule(stdecomp_handle* h, int64_t epoch) {
   HIPCHK(h, stdk::launch_perm_gather(h->s, h->coo, h->coo_perm, h->T, h->seed_sample, epoch, h->stream));
-  HIPCHK(h, stdk::launch_sort(h->s, h->coo_perm, h->sigma, h->xrow, h->nseg, h->rec_sorted, h->W, h->chunk, h->T,
+  HIPCHK(h, stdk::launch_sort(h->s, h->coo_perm, h->sigma, h->xrow, h->nseg, h->rec_sorted, h->meta, h->W, h->chunk, h->T,
                               h->M, 0, h->nb, h->stream));
   h->sched_epoch = epoch;
   return STD_OK;
@@ -303,6 +314,8 @@ void release(stdecomp_handle* h) {
   dfree(h->rec_sorted);
   dfree(h->xrow);
   dfree(h->nseg);
+  dfree(h->meta);
+  dfree(h->aux);
   for (int n = 0; n < kMaxOrder; ++n) {
     dfree(h->A[n]);
     dfree(h->Ab[n]);
@@ -444,7 +457,8 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   const size_t T = (size_t)h->T;
   if ((rc = dalloc(h, &h->coo, T * s.R)) || (rc = dalloc(h, &h->coo_perm, T * s.R)) ||
       (rc = dalloc(h, &h->sigma, T * N)) || (rc = dalloc(h, &h->rec_sorted, T * N * s.R)) ||
-      (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * h->W)) ||
+      (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * stdk::xrow_stride(h->W))) ||
+      (rc = dalloc(h, &h->meta, T * N)) || (rc = dalloc(h, &h->aux, h->aux_host.size())) ||
       (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
       (rc = dalloc(h, &h->partial, (size_t)h->W * stdk::pad4((int)P))) ||
       (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||
@@ -460,7 +474,9 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       return bail(STD_E_DEVICE);
     }
   }
-  if (hipMemsetAsync(h->xrow, 0xFF, (size_t)h->nb * N * h->W * 4, h->stream) != hipSuccess) {
+  if (hipMemsetAsync(h->xrow, 0xFF, (size_t)h->nb * N * stdk::xrow_stride(h->W) * 4, h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->aux, h->aux_host.data(), h->aux_host.size() * 4, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess) {
     h->last_error = "hipMemset failed";
     return bail(STD_E_DEVICE);
   }

@@ -98,8 +98,9 @@ hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* ou
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restrict__ coo, uint16_t* __restrict__ sigma,
                                                        int* __restrict__ xrow, int* __restrict__ nseg,
-                                                       uint32_t* __restrict__ rec_sorted, int64_t T, int64_t M,
-                                                       int64_t b_begin, int R, int N, int W, int chunk) {
+                                                       uint32_t* __restrict__ rec_sorted, uint16_t* __restrict__ meta,
+                                                       int64_t T, int64_t M, int64_t b_begin, int R, int N, int W,
+                                                       int chunk) {
   extern __shared__ unsigned long long keys[];
   __shared__ int heads;
   const int64_t b = b_begin + blockIdx.x;
@@ -160,6 +161,52 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restric
     for (int i = 0; i < ITEMS; ++i) keys[out0 + i] = k[i];
     __syncthreads();
   }
+  // Run metadata for the chain (thread tid holds the sorted positions
+  // [tid*ITEMS, (tid+1)*ITEMS) in k[]): the start of each position's row run
+  // is the last head at or before it, a block-wide max-scan.
+  {
+    __shared__ int wtot[kSortThreads / 64];
+    const int out0 = tid * ITEMS;
+    const int lane = tid & 63, wv = tid >> 6;
+    const unsigned long long before_key = out0 > 0 ? keys[out0 - 1] : ~0ull;
+    const unsigned long long after_key = out0 + ITEMS < CAP ? keys[out0 + ITEMS] : ~0ull;
+    int last = -1;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int pos = out0 + i;
+      const unsigned long long pk = (i == 0) ? before_key : k[i - 1];
+      if (pos < m && (pos == 0 || (pk >> 16) != (k[i] >> 16))) last = pos;
+    }
+    int incl = last;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = __shfl_up(incl, d);
+      if (lane >= d) incl = max(incl, o);
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int st = __shfl_up(incl, 1);
+    if (lane == 0) st = -1;
+    for (int v = 0; v < wv; ++v) st = max(st, wtot[v]);
+    uint16_t* mt = meta + (int64_t)n * T + base;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int pos = out0 + i;
+      if (pos < m) {
+        const unsigned long long pk = (i == 0) ? before_key : k[i - 1];
+        const unsigned long long nk = (i + 1 < ITEMS) ? k[i + 1] : after_key;
+        if (pos == 0 || (pk >> 16) != (k[i] >> 16)) st = pos;
+        const int qlo = (pos / chunk) * chunk;
+        const int sf = max(st, qlo) - qlo;
+        const bool next_same = pos + 1 < m && (nk >> 16) == (k[i] >> 16);
+        const bool chunk_end = pos + 1 == qlo + chunk;
+        int v = sf;
+        if (!next_same || chunk_end) v |= kMetaTail;
+        if (sf == 0 && st < qlo) v |= kMetaBefore;
+        if (chunk_end && next_same) v |= kMetaAfter;
+        mt[pos] = (uint16_t)v;
+      }
+    }
+  }
   uint16_t* out = sigma + (int64_t)n * T + base;
   if (tid == 0) heads = 0;
   __syncthreads();
@@ -176,37 +223,47 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restric
   __syncthreads();
   if (tid == 0) nseg[b * N + n] = heads;
   // Chunk boundaries of the chain: the row that straddles boundary bw (the
-  // positions bw*chunk - 1 and bw*chunk share it), or -1.
+  // positions bw*chunk - 1 and bw*chunk share it) or -1; then, for the first
+  // boundary of each straddling row, its entry number; then their count.
   if (W > 1) {
-    int* xr = xrow + ((size_t)b * N + n) * W;
-    for (int bw = tid; bw < W; bw += kSortThreads) {
+    int* xr = xrow + ((size_t)b * N + n) * xrow_stride(W);
+    auto straddle = [&](int bw) {
       const int q = bw * chunk;
-      int v = -1;
       if (bw > 0 && q < m) {
         const unsigned long long r0 = keys[q - 1] >> 16, r1 = keys[q] >> 16;
-        if (r0 == r1) v = (int)r1;
+        if (r0 == r1) return (int)r1;
       }
-      xr[bw] = v;
+      return -1;
+    };
+    for (int bw = tid; bw < W; bw += kSortThreads) xr[bw] = straddle(bw);
+    if (tid == 0) {
+      int cnt = 0, prev = -1;
+      for (int bw = 0; bw < W; ++bw) {
+        const int v = straddle(bw);
+        xr[W + bw] = (v >= 0 && v != prev) ? cnt++ : -1;
+        prev = v;
+      }
+      xr[2 * W] = cnt;
     }
   }
 }
 
 hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg,
-                       uint32_t* rec_sorted, int W, int chunk, int64_t T, int64_t M, int64_t b_begin, int64_t b_end,
-                       hipStream_t st) {
+                       uint32_t* rec_sorted, uint16_t* meta, int W, int chunk, int64_t T, int64_t M,
+                       int64_t b_begin, int64_t b_end, hipStream_t st) {
   const int64_t nb = b_end - b_begin;
   if (nb <= 0) return hipSuccess;
   for (int64_t b0 = 0; b0 < nb; b0 += 65535) {
     const int g = (int)((nb - b0 < 65535) ? nb - b0 : 65535);
     dim3 grid(g, s.N);
     if (M <= 1024) {
-      hipLaunchKernelGGL(k_sort<4>, grid, dim3(kSortThreads), 1024 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, T, M, b_begin + b0, s.R, s.N, W, chunk);
+      hipLaunchKernelGGL(k_sort<4>, grid, dim3(kSortThreads), 1024 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, meta, T, M, b_begin + b0, s.R, s.N, W, chunk);
     } else if (M <= 4096) {
-      hipLaunchKernelGGL(k_sort<16>, grid, dim3(kSortThreads), 4096 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, T, M, b_begin + b0, s.R, s.N, W, chunk);
+      hipLaunchKernelGGL(k_sort<16>, grid, dim3(kSortThreads), 4096 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, meta, T, M, b_begin + b0, s.R, s.N, W, chunk);
     } else {
       hipError_t e = hipFuncSetAttribute((const void*)k_sort<64>, hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 8);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_sort<64>, grid, dim3(kSortThreads), 16384 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, T, M, b_begin + b0, s.R, s.N, W, chunk);
+      hipLaunchKernelGGL(k_sort<64>, grid, dim3(kSortThreads), 16384 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, meta, T, M, b_begin + b0, s.R, s.N, W, chunk);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
