@@ -61,7 +61,7 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 // in between.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void barrier_arrive(const ChainArgs& a, unsigned passed) {
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0)
     __hip_atomic_store(a.bar + blockIdx.x * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -101,8 +101,9 @@ __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed
 // Every field is read from memory at a uniform offset, so no register array
 // is ever indexed at run time.
 // ---------------------------------------------------------------------------
+template <int NM>
 struct LaneRec {
-  int idx[kMaxOrder];  // the N indices (only read at compile-time positions)
+  int idx[NM];         // the N indices (only read at compile-time positions)
   float x;             // the value
   int rown;            // index in the phase's mode n
   int rpm;             // index in the mode the previous phase updated (or -1)
@@ -110,14 +111,15 @@ struct LaneRec {
   bool valid;
 };
 
-__device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int64_t b, int ph, LaneRec& r) {
+template <int NM>
+__device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int N, int64_t b, int ph, LaneRec<NM>& r) {
   const PhaseTab& pt = a.pt[ph];
   const int64_t base = b * a.M;
   const int m = (int)((a.T - base < a.M) ? (a.T - base) : a.M);
   const int q = blockIdx.x * a.chunk + (int)threadIdx.x;
   r.valid = (int)threadIdx.x < a.chunk && q < m;
 #pragma unroll
-  for (int k = 0; k < kMaxOrder; ++k) r.idx[k] = 0;
+  for (int k = 0; k < NM; ++k) r.idx[k] = 0;
   r.x = 0.f;
   r.rown = 0;
   r.rpm = -1;
@@ -126,8 +128,8 @@ __device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int64_t b, int
     const uint32_t* src = (ph == 0) ? a.coo + (base + q) * a.s.R
                                     : a.rec_sorted + ((int64_t)(ph - 1) * a.T + base + q) * a.s.R;
 #pragma unroll
-    for (int k = 0; k < kMaxOrder; ++k)
-      if (k < a.s.N) r.idx[k] = (int)src[k];
+    for (int k = 0; k < NM; ++k)
+      if (k < N) r.idx[k] = (int)src[k];
     r.x = __uint_as_float(src[a.s.R - 1]);
     r.rown = (int)src[pt.n];
     if (pt.pm >= 0) r.rpm = (int)src[pt.pm];
@@ -145,33 +147,34 @@ struct RowRegs {
   u32x4 v[NS > 0 ? NS : 1][C];
 };
 
-template <int JR, bool BF, int NS, int K0>
-__device__ __forceinline__ void issue_rows(const ChainArgs& a, const int (&idx)[kMaxOrder], unsigned mask,
+// (EXACT: every J_k equals JR, so the row lengths are compile-time constants)
+template <int JR, bool BF, bool EXACT, int NM, int NS, int K0>
+__device__ __forceinline__ void issue_rows(const ChainArgs& a, const int (&idx)[NM], unsigned mask,
                                            RowRegs<JR, BF, NS>& rr) {
   constexpr int C = RowRegs<JR, BF, NS>::C;
   constexpr int PER = BF ? 8 : 4;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int k = K0 + i;
-    if (k < kMaxOrder && ((mask >> k) & 1u)) {
+    if (k < NM && ((mask >> k) & 1u)) {
       const u32x4* src = BF ? reinterpret_cast<const u32x4*>(a.Ab[k] + (int64_t)idx[k] * a.Jb[k])
                             : reinterpret_cast<const u32x4*>(a.A[k] + (int64_t)idx[k] * a.s.Jp[k]);
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        if (PER * c < a.s.J[k]) rr.v[i][c] = src[c];
+        if (EXACT || PER * c < a.s.J[k]) rr.v[i][c] = src[c];
     }
   }
 }
 
-template <int JR, bool BF, int NS, int K0>
+template <int JR, bool BF, bool EXACT, int NM, int NS, int K0>
 __device__ __forceinline__ void store_rows(const ChainArgs& a, unsigned mask, const RowRegs<JR, BF, NS>& rr,
                                            float* rb) {
   constexpr int C = RowRegs<JR, BF, NS>::C;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int k = K0 + i;
-    if (k < kMaxOrder && ((mask >> k) & 1u)) {
-      const int J = a.s.J[k];
+    if (k < NM && ((mask >> k) & 1u)) {
+      const int J = EXACT ? JR : a.s.J[k];
       float* dst = rb + a.s.rs_off[k];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -194,33 +197,33 @@ __device__ __forceinline__ void store_rows(const ChainArgs& a, unsigned mask, co
 
 // All rows of `mask` for one sample into its LDS row buffer, staged so that
 // at most 16 vectors are in registers at once.
-template <int JR, bool BF>
-__device__ __forceinline__ void gather_rows(const ChainArgs& a, const int (&idx)[kMaxOrder], unsigned mask, float* rb) {
+template <int JR, bool BF, bool EXACT, int NM>
+__device__ __forceinline__ void gather_rows(const ChainArgs& a, const int (&idx)[NM], unsigned mask, float* rb) {
   constexpr int C = RowRegs<JR, BF, 1>::C;
-  constexpr int SP = (16 / C) < kMaxOrder ? (16 / C) : kMaxOrder;
-  static_assert(4 * SP >= kMaxOrder, "four stages cover every mode");
+  constexpr int SP = (16 / C) < NM ? (16 / C) : NM;
+  static_assert(4 * SP >= NM, "four stages cover every mode");
   RowRegs<JR, BF, SP> r0;
-  issue_rows<JR, BF, SP, 0>(a, idx, mask, r0);
-  store_rows<JR, BF, SP, 0>(a, mask, r0, rb);
-  if constexpr (SP < kMaxOrder) {
+  issue_rows<JR, BF, EXACT, NM, SP, 0>(a, idx, mask, r0);
+  store_rows<JR, BF, EXACT, NM, SP, 0>(a, mask, r0, rb);
+  if constexpr (SP < NM) {
     if (mask >> SP) {
       RowRegs<JR, BF, SP> r1;
-      issue_rows<JR, BF, SP, SP>(a, idx, mask, r1);
-      store_rows<JR, BF, SP, SP>(a, mask, r1, rb);
+      issue_rows<JR, BF, EXACT, NM, SP, SP>(a, idx, mask, r1);
+      store_rows<JR, BF, EXACT, NM, SP, SP>(a, mask, r1, rb);
     }
   }
-  if constexpr (2 * SP < kMaxOrder) {
+  if constexpr (2 * SP < NM) {
     if (mask >> (2 * SP)) {
       RowRegs<JR, BF, SP> r2;
-      issue_rows<JR, BF, SP, 2 * SP>(a, idx, mask, r2);
-      store_rows<JR, BF, SP, 2 * SP>(a, mask, r2, rb);
+      issue_rows<JR, BF, EXACT, NM, SP, 2 * SP>(a, idx, mask, r2);
+      store_rows<JR, BF, EXACT, NM, SP, 2 * SP>(a, mask, r2, rb);
     }
   }
-  if constexpr (3 * SP < kMaxOrder) {
+  if constexpr (3 * SP < NM) {
     if (mask >> (3 * SP)) {
       RowRegs<JR, BF, SP> r3;
-      issue_rows<JR, BF, SP, 3 * SP>(a, idx, mask, r3);
-      store_rows<JR, BF, SP, 3 * SP>(a, mask, r3, rb);
+      issue_rows<JR, BF, EXACT, NM, SP, 3 * SP>(a, idx, mask, r3);
+      store_rows<JR, BF, EXACT, NM, SP, 3 * SP>(a, mask, r3, rb);
     }
   }
 }
@@ -236,7 +239,7 @@ template <int JR, bool EXACT, bool BF>
 __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
                                   const float* cbuf, float* split, int sstride, bool store) {
   const int tid = threadIdx.x, BT = blockDim.x;
-  const int pJ = a.s.J[pm];
+  const int pJ = EXACT ? JR : a.s.J[pm];
   for (int bw = tid + 1; bw < a.W; bw += BT) {
     const int e = xn[bw];
     if (e < 0) continue;
@@ -289,10 +292,13 @@ __device__ __forceinline__ void build_table_map(const float* Gs, const int* tmap
   for (int e0 = threadIdx.x; e0 < len; e0 += 4 * BT) {
     int o[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) o[u] = (e0 + u * BT < len) ? tmap[e0 + u * BT] : -1;
+    for (int u = 0; u < 4; ++u) o[u] = tmap[min(e0 + u * BT, len - 1)];
     float v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = o[u] >= 0 ? Gs[o[u]] : 0.f;
+    for (int u = 0; u < 4; ++u) {
+      const float g = Gs[max(o[u], 0)];
+      v[u] = o[u] >= 0 ? g : 0.f;
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = e0 + u * BT;
@@ -384,32 +390,38 @@ __device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, con
 // E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
 // header).  Each wave carries two 16-sample tiles at once so that two
 // independent MFMA chains overlap.
-template <int JR, bool BF>
+template <int JR, bool BF, bool EXACT>
 __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf, const float* hp,
                        int cnt, int chp, float* ebuf, int es) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int Jn = g.Jn;
+  constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
+  const int Jn = EXACT ? JR : g.Jn;
   const int MT = (cnt + 15) >> 4;
   const int lo_off = g.rs_lo;
-  const int khi = g.khi, kp = g.kp, nt = g.nt, jlo = g.jlo;
+  const int khi = g.khi;
+  const int kp = EXACT ? KPX : g.kp;
+  const int nt = EXACT ? (JR + 15) / 16 : g.nt;
+  const int jlo = EXACT ? JR : g.jlo;
   const int jobs = ((MT + 1) >> 1) * nt;  // job = (tile pair, j_n tile)
   for (int job = wv; job < jobs; job += nwaves) {
     const int mp = job / nt, t = job - mp * nt;
     const int mt0 = 2 * mp, mt1 = 2 * mp + 1;
     const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
+    const int prow0c = min(prow0, chp - 1), prow1c = min(prow1, chp - 1);
     f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
     const float* hp0 = hp + mt0 * 16 + 4 * kq;
-    const float* hp1 = hp + mt1 * 16 + 4 * kq;  // within chp: chp is a multiple of 16 and covers mt1 when used
-    const bool has1 = mt1 < MT;
+    const float* hp1 = hp + min(mt1, MT - 1) * 16 + 4 * kq;  // (tile mt1 is masked when it does not exist)
     if constexpr (!BF) {
       constexpr int KS = (JR + 3) / 4;
       float a0[KS], a1[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
+        // no masks: the table rows k >= J_lo are zero, samples p >= cnt are
+        // not stored, and the row buffer holds finite values only
         const int k = 4 * ks + kq;
-        a0[ks] = (prow0 < cnt && k < jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f;
-        a1[ks] = (prow1 < cnt && k < jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f;
+        a0[ks] = rowbuf[prow0c * s.rs + lo_off + k];
+        a1[ks] = rowbuf[prow1c * s.rs + lo_off + k];
       }
       const int nks = kp >> 2;
       const float* tb = TB + (t * kp + kq) * 16 + r16;
@@ -429,26 +441,26 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bw, d1, 0, 0, 0);
           }
         }
-        const float4 h0 = *reinterpret_cast<const float4*>(hp0 + h * chp);
-        const float4 g0 = *reinterpret_cast<const float4*>(hp0 + (h + 1) * chp);
-        const float4 h1 = has1 ? *reinterpret_cast<const float4*>(hp1 + h * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 g1 = has1 ? *reinterpret_cast<const float4*>(hp1 + (h + 1) * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
-        e0[0] = fmaf(c0[0], h0.x, e0[0]);
-        e0[1] = fmaf(c0[1], h0.y, e0[1]);
-        e0[2] = fmaf(c0[2], h0.z, e0[2]);
-        e0[3] = fmaf(c0[3], h0.w, e0[3]);
-        e1[0] = fmaf(c1[0], h1.x, e1[0]);
-        e1[1] = fmaf(c1[1], h1.y, e1[1]);
-        e1[2] = fmaf(c1[2], h1.z, e1[2]);
-        e1[3] = fmaf(c1[3], h1.w, e1[3]);
-        e0[0] = fmaf(d0[0], g0.x, e0[0]);
-        e0[1] = fmaf(d0[1], g0.y, e0[1]);
-        e0[2] = fmaf(d0[2], g0.z, e0[2]);
-        e0[3] = fmaf(d0[3], g0.w, e0[3]);
-        e1[0] = fmaf(d1[0], g1.x, e1[0]);
-        e1[1] = fmaf(d1[1], g1.y, e1[1]);
-        e1[2] = fmaf(d1[2], g1.z, e1[2]);
-        e1[3] = fmaf(d1[3], g1.w, e1[3]);
+        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
+        const f32x4 g0 = *reinterpret_cast<const f32x4*>(hp0 + (h + 1) * chp);
+        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
+        const f32x4 g1 = *reinterpret_cast<const f32x4*>(hp1 + (h + 1) * chp);
+        e0[0] = fmaf(c0[0], h0[0], e0[0]);
+        e0[1] = fmaf(c0[1], h0[1], e0[1]);
+        e0[2] = fmaf(c0[2], h0[2], e0[2]);
+        e0[3] = fmaf(c0[3], h0[3], e0[3]);
+        e1[0] = fmaf(c1[0], h1[0], e1[0]);
+        e1[1] = fmaf(c1[1], h1[1], e1[1]);
+        e1[2] = fmaf(c1[2], h1[2], e1[2]);
+        e1[3] = fmaf(c1[3], h1[3], e1[3]);
+        e0[0] = fmaf(d0[0], g0[0], e0[0]);
+        e0[1] = fmaf(d0[1], g0[1], e0[1]);
+        e0[2] = fmaf(d0[2], g0[2], e0[2]);
+        e0[3] = fmaf(d0[3], g0[3], e0[3]);
+        e1[0] = fmaf(d1[0], g1[0], e1[0]);
+        e1[1] = fmaf(d1[1], g1[1], e1[1]);
+        e1[2] = fmaf(d1[2], g1[2], e1[2]);
+        e1[3] = fmaf(d1[3], g1[3], e1[3]);
       }
       for (; h < khi; ++h) {
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
@@ -460,16 +472,16 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, c1, 0, 0, 0);
           }
         }
-        const float4 h0 = *reinterpret_cast<const float4*>(hp0 + h * chp);
-        const float4 h1 = has1 ? *reinterpret_cast<const float4*>(hp1 + h * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
-        e0[0] = fmaf(c0[0], h0.x, e0[0]);
-        e0[1] = fmaf(c0[1], h0.y, e0[1]);
-        e0[2] = fmaf(c0[2], h0.z, e0[2]);
-        e0[3] = fmaf(c0[3], h0.w, e0[3]);
-        e1[0] = fmaf(c1[0], h1.x, e1[0]);
-        e1[1] = fmaf(c1[1], h1.y, e1[1]);
-        e1[2] = fmaf(c1[2], h1.z, e1[2]);
-        e1[3] = fmaf(c1[3], h1.w, e1[3]);
+        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
+        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
+        e0[0] = fmaf(c0[0], h0[0], e0[0]);
+        e0[1] = fmaf(c0[1], h0[1], e0[1]);
+        e0[2] = fmaf(c0[2], h0[2], e0[2]);
+        e0[3] = fmaf(c0[3], h0[3], e0[3]);
+        e1[0] = fmaf(c1[0], h1[0], e1[0]);
+        e1[1] = fmaf(c1[1], h1[1], e1[1]);
+        e1[2] = fmaf(c1[2], h1[2], e1[2]);
+        e1[3] = fmaf(c1[3], h1[3], e1[3]);
       }
     } else {
       constexpr int KS = (JR + 15) / 16;
@@ -479,8 +491,8 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k = 16 * ks + 4 * kq + e;
-          a0[ks][e] = (short)bf16_bits((prow0 < cnt && k < jlo) ? rowbuf[prow0 * s.rs + lo_off + k] : 0.f);
-          a1[ks][e] = (short)bf16_bits((prow1 < cnt && k < jlo) ? rowbuf[prow1 * s.rs + lo_off + k] : 0.f);
+          a0[ks][e] = (short)bf16_bits(rowbuf[prow0c * s.rs + lo_off + k]);
+          a1[ks][e] = (short)bf16_bits(rowbuf[prow1c * s.rs + lo_off + k]);
         }
       }
       const int nks = kp >> 4;
@@ -496,16 +508,16 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
           }
         }
-        const float4 h0 = *reinterpret_cast<const float4*>(hp0 + h * chp);
-        const float4 h1 = has1 ? *reinterpret_cast<const float4*>(hp1 + h * chp) : make_float4(0.f, 0.f, 0.f, 0.f);
-        e0[0] = fmaf(c0[0], h0.x, e0[0]);
-        e0[1] = fmaf(c0[1], h0.y, e0[1]);
-        e0[2] = fmaf(c0[2], h0.z, e0[2]);
-        e0[3] = fmaf(c0[3], h0.w, e0[3]);
-        e1[0] = fmaf(c1[0], h1.x, e1[0]);
-        e1[1] = fmaf(c1[1], h1.y, e1[1]);
-        e1[2] = fmaf(c1[2], h1.z, e1[2]);
-        e1[3] = fmaf(c1[3], h1.w, e1[3]);
+        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
+        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
+        e0[0] = fmaf(c0[0], h0[0], e0[0]);
+        e0[1] = fmaf(c0[1], h0[1], e0[1]);
+        e0[2] = fmaf(c0[2], h0[2], e0[2]);
+        e0[3] = fmaf(c0[3], h0[3], e0[3]);
+        e1[0] = fmaf(c1[0], h1[0], e1[0]);
+        e1[1] = fmaf(c1[1], h1[1], e1[1]);
+        e1[2] = fmaf(c1[2], h1[2], e1[2]);
+        e1[3] = fmaf(c1[3], h1[3], e1[3]);
       }
     }
     const int jn = 16 * t + r16;
@@ -523,14 +535,15 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 // p >= cnt).  Jobs are (h, j0 tile, j_lo tile); a wave carries up to three
 // jobs with the same tiles and consecutive h at once, which share the A row
 // and B column loads and keep three independent MFMA chains in flight.
-template <bool BF>
+template <int JR, bool BF, bool EXACT>
 __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra, int ras,
                                const float* hp, int cnt, int chp, float* out) {
   constexpr int JG = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int J0 = g.Jn;  // the core phase contracts with mode 0
-  const int jlo = g.jlo, khi = g.khi;
+  const int J0 = EXACT ? JR : g.Jn;  // the core phase contracts with mode 0
+  const int jlo = EXACT ? JR : g.jlo;
+  const int khi = g.khi;
   const int MT0 = (J0 + 15) >> 4, NT1 = (jlo + 15) >> 4;
   const int lo_off = g.rs_lo;
   const int hgroups = (khi + JG - 1) / JG;
@@ -543,7 +556,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
     const int t0 = rem / NT1, t1 = rem - t0 * NT1;
     const int j0 = 16 * t0 + r16;  // A row
     const int jl = 16 * t1 + r16;  // B column
-    const bool arow = j0 < J0, bcol = jl < jlo;
+    const bool bcol = jl < jlo;
     const int h0 = hg * JG;
     const float* hph[JG];
     bool hok[JG];
@@ -556,13 +569,17 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
 #pragma unroll
     for (int q = 0; q < JG; ++q) c[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF) {
-      // operands of step st+1 are read before the MFMAs of step st
+      // Operands of step st+1 are read before the MFMAs of step st.  No
+      // masks: p < chp always (4 * nsteps <= chp); positions p >= cnt have
+      // zero r a(0) and zero hp, and the row buffer holds finite values
+      // only; rows j0 >= J0 and columns jl >= J_lo reach only outputs that
+      // are not stored.
       auto load = [&](int st, float& rav, float& bv, float (&hv)[JG]) {
         const int p = st * 4 + kq;
-        rav = (arow && p < chp) ? ra[p * ras + j0] : 0.f;
-        bv = (bcol && p < cnt) ? rowbuf[p * s.rs + lo_off + jl] : 0.f;
+        rav = ra[p * ras + j0];
+        bv = rowbuf[p * s.rs + lo_off + jl];
 #pragma unroll
-        for (int q = 0; q < JG; ++q) hv[q] = (p < chp) ? hph[q][p] : 0.f;
+        for (int q = 0; q < JG; ++q) hv[q] = hph[q][p];
       };
       float rav, bv, hv[JG];
       if (nsteps > 0) load(0, rav, bv, hv);
@@ -583,10 +600,10 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
         float rav[4];
         s16x4 bv;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 4; ++e) {  // no masks (see the FP32 path); 16 * nsteps <= chp
           const int p = st * 16 + 4 * kq + e;
-          rav[e] = (arow && p < chp) ? ra[p * ras + j0] : 0.f;
-          bv[e] = (short)bf16_bits((bcol && p < cnt) ? rowbuf[p * s.rs + lo_off + jl] : 0.f);
+          rav[e] = ra[p * ras + j0];
+          bv[e] = (short)bf16_bits(rowbuf[p * s.rs + lo_off + jl]);
         }
 #pragma unroll
         for (int q = 0; q < JG; ++q) {
@@ -594,7 +611,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int p = st * 16 + 4 * kq + e;
-            av[e] = (short)bf16_bits(p < chp ? rav[e] * hph[q][p] : 0.f);
+            av[e] = (short)bf16_bits(rav[e] * hph[q][p]);
           }
           c[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c[q], 0, 0, 0);
         }
@@ -651,17 +668,18 @@ __device__ __forceinline__ void copy_carry(const ChainArgs& a, int par, float* c
 //   that follows).
 // Carry slot: [0] row, [1] count, [2, 2+J) partial sum, [2+J, 2+2J) old row.
 // ---------------------------------------------------------------------------
-template <int JU, int BFI>
+template <int JU, int NU, int BFI>
 __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   constexpr int JR = JU ? JU : kMaxRank;
+  constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
   constexpr bool BF = BFI != 0;
   constexpr int CV = RowRegs<JR, BF, 1>::C;
   // modes whose rows are parked in registers between sub-steps (generic ranks: none)
-  constexpr int NPF = EXACT ? ((12 / CV) < kMaxOrder ? (12 / CV) : kMaxOrder) : 0;
+  constexpr int NPF = EXACT ? ((12 / CV) < NM ? (12 / CV) : NM) : 0;
   extern __shared__ float lds[];
   const Shape& s = a.s;
-  const int N = s.N;
+  const int N = NU ? NU : s.N;
   const int P = s.P;
   const int Pp = pad4(P);
   const int tid = threadIdx.x;
@@ -695,6 +713,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 
   // ---- set-up: core, index maps, resident tables
   for (int lin = tid; lin < P; lin += BT) Gs[lin] = a.G[lin];
+  for (int i = tid; i < chp * s.rs; i += BT) rowbuf[i] = 0.f;
   for (int i = tid; i < L.aux_len; i += BT) {
     const int v = a.aux[i];
     if (i < L.hm_len) hmap[i] = v;
@@ -713,8 +732,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   int par = 0;   // carry parity of the current phase
   bool first = true;
 
-  LaneRec cur;
-  if (a.b_begin < a.b_end) load_lane_rec(a, a.b_begin, 0, cur);
+  LaneRec<NM> cur;
+  if (a.b_begin < a.b_end) load_lane_rec<NM>(a, N, a.b_begin, 0, cur);
   else cur.valid = false;
   RowRegs<JR, BF, NPF> pf;   // next phase's rows, loaded during this phase
   float an_cur[JR], an_nxt[JR];  // BF16 mode: FP32 master row of the lane's own-mode row
@@ -765,7 +784,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           for (int v = 0; v < 8; ++v)
             if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
         }
-        if (active) gather_rows<JR, BF>(a, cur.idx, post, rb);
+        if (active) gather_rows<JR, BF, EXACT, NM>(a, cur.idx, post, rb);
         if (splits) {
           f32x4* cdst = reinterpret_cast<f32x4*>(cbuf);
 #pragma unroll
@@ -787,8 +806,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         ++nbb;
       }
       const bool has_next = nbb < a.b_end;
-      LaneRec nx;
-      if (has_next) load_lane_rec(a, nbb, nph, nx);
+      LaneRec<NM> nx;
+      if (has_next) load_lane_rec<NM>(a, N, nbb, nph, nx);
       else nx.valid = false;
       __syncthreads();
 
@@ -804,8 +823,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
               if (v < a.W) sum += pp[v];
             v0 = 8;
           }
-#pragma unroll 16
-          for (int v = v0; v < a.W; ++v) sum += psrc[(size_t)v * P4 + l4];
+          for (int vb = v0; vb < a.W; vb += 16) {  // 16 loads in flight, summed in order
+            f32x4 t[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) t[u] = psrc[(size_t)min(vb + u, a.W - 1) * P4 + l4];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+              if (vb + u < a.W) sum += t[u];
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int lin = 4 * l4 + i;
@@ -827,7 +852,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
         if (active && nsplit > 0) {
           // the table follows the chunk boundaries, so its rows are increasing
-          const int pJ = s.J[pm];
+          const int pJ = EXACT ? JR : s.J[pm];
           const int prow = cur.rpm;
           int lo2 = 0, hi2 = nsplit;
           while (lo2 < hi2) {
@@ -837,9 +862,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           }
           if (lo2 < nsplit && __float_as_int(split[lo2 * sstride]) == prow) {
             float* dst = rb + s.rs_off[pm];
-            for (int j = 0; j < pJ; ++j) {
-              const float v = split[lo2 * sstride + 4 + j];
-              dst[j] = BF ? bf16_round(v) : v;
+#pragma unroll
+            for (int j = 0; j < JR; ++j) {
+              if (EXACT || j < pJ) {
+                const float v = split[lo2 * sstride + 4 + j];
+                dst[j] = BF ? bf16_round(v) : v;
+              }
             }
           }
         }
@@ -848,10 +876,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       // ---- 4. the next phase's rows that no phase writes before it: into registers
       unsigned pre = 0;
       if (has_next) pre = (allm & ~(unsigned)a.pt[nph].post) & npfm;
-      if (NPF > 0 && nx.valid && pre) issue_rows<JR, BF, NPF, 0>(a, nx.idx, pre, pf);
+      if (NPF > 0 && nx.valid && pre) issue_rows<JR, BF, EXACT, NM, NPF, 0>(a, nx.idx, pre, pf);
       if (BF && has_next && nx.valid && nph > 0) {
         const float* src = a.A[a.pt[nph].n] + (int64_t)nx.rown * s.Jp[a.pt[nph].n];
-        const int Jx = a.pt[nph].Jn;
+        const int Jx = EXACT ? JR : a.pt[nph].Jn;
 #pragma unroll
         for (int j = 0; j < JR; ++j)
           if (EXACT || j < Jx) an_nxt[j] = src[j];
@@ -861,7 +889,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       build_hp(s, pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
-      mfma_E<JR, BF>(s, pt, TBn, rowbuf, hp, cnt, chp, ebuf, es);
+      mfma_E<JR, BF, EXACT>(s, pt, TBn, rowbuf, hp, cnt, chp, ebuf, es);
       __syncthreads();
 
       if (ph == 0) {
@@ -881,7 +909,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
         __syncthreads();
         // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
-        mfma_core_grad<BF>(s, pt, rowbuf, rabuf, ras, hp, cnt, chp, a.partial + (size_t)w * Pp);
+        mfma_core_grad<JR, BF, EXACT>(s, pt, rowbuf, rabuf, ras, hp, cnt, chp, a.partial + (size_t)w * Pp);
       } else {
         // ================= mode-n sub-step =================
         float u[JR], an[JR];
@@ -968,7 +996,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       //      core update changed (neither reads what other workgroups write).
       passed += 1;
       barrier_arrive(a, passed);
-      if (NPF > 0 && nx.valid && pre) store_rows<JR, BF, NPF, 0>(a, pre, pf, rb);
+      if (NPF > 0 && nx.valid && pre) store_rows<JR, BF, EXACT, NM, NPF, 0>(a, pre, pf, rb);
       if (ph == 1 && L.tb_all) {
         for (int n2 = 1; n2 < N; ++n2) {
           const PhaseTab& q = a.pt[n2 + 1];
@@ -1145,6 +1173,26 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
 
 size_t chain_lds_bytes(const ChainArgs& a, int threads) { return (size_t)a.lay.total * 4; }
 
+template <int JU, int NU, int BFI>
+hipError_t launch_chain_t(const ChainArgs& a, int threads, size_t bytes, hipStream_t st) {
+  ChainArgs args = a;
+  void* params[] = {&args};
+  hipError_t e = hipFuncSetAttribute((const void*)k_chain<JU, NU, BFI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
+  if (e == hipSuccess)
+    e = hipLaunchCooperativeKernel((const void*)k_chain<JU, NU, BFI>, dim3(a.W), dim3(threads), params,
+                                   (unsigned)bytes, st);
+  return e;
+}
+
+// three-mode tensors get a kernel with the mode loops unrolled
+template <int JU>
+hipError_t launch_chain_n(const ChainArgs& a, int threads, size_t bytes, hipStream_t st, int bf) {
+  const bool n3 = a.s.N == 3;
+  if (bf) return n3 ? launch_chain_t<JU, 3, 1>(a, threads, bytes, st) : launch_chain_t<JU, 0, 1>(a, threads, bytes, st);
+  return n3 ? launch_chain_t<JU, 3, 0>(a, threads, bytes, st) : launch_chain_t<JU, 0, 0>(a, threads, bytes, st);
+}
+
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
   const int var = chain_variant(a.s);
   const size_t bytes = (size_t)a.lay.total * 4;
@@ -1152,27 +1200,14 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
     ChainArgs chk = a;
     if (plan_chain_lds(chk, threads, a.bf16 != 0) != bytes || chk.lay.cbuf != a.lay.cbuf ||
         chk.lay.ints != a.lay.ints || chk.lay.tmap != a.lay.tmap || chk.lay.aux_len != a.lay.aux_len ||
-        chk.lay.hm_len != a.lay.hm_len ||
-        !a.aux)
+        chk.lay.hm_len != a.lay.hm_len || !a.aux)
       return hipErrorInvalidValue;
   }
   hipError_t e = hipSuccess;
-  ChainArgs args = a;
-  void* params[] = {&args};
   if (a.bf16) {
-    STDK_FOR_VARIANT(var, {
-      e = hipFuncSetAttribute((const void*)k_chain<JU, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-      if (e == hipSuccess)
-        e = hipLaunchCooperativeKernel((const void*)k_chain<JU, 1>, dim3(a.W), dim3(threads), params, (unsigned)bytes,
-                                       st);
-    });
+    STDK_FOR_VARIANT(var, { e = launch_chain_n<JU>(a, threads, bytes, st, 1); });
   } else {
-    STDK_FOR_VARIANT(var, {
-      e = hipFuncSetAttribute((const void*)k_chain<JU, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-      if (e == hipSuccess)
-        e = hipLaunchCooperativeKernel((const void*)k_chain<JU, 0>, dim3(a.W), dim3(threads), params, (unsigned)bytes,
-                                       st);
-    });
+    STDK_FOR_VARIANT(var, { e = launch_chain_n<JU>(a, threads, bytes, st, 0); });
   }
   return e;
 }
