@@ -41,6 +41,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
+// Zero words after the LDS row buffer: the MFMA K steps of the contraction
+// read up to 31 words past a sample's lo-mode row (multiplied by zero table
+// rows), so everything they can reach must hold finite values.
+constexpr int kRowTail = 32;
+
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
   if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (unsigned short)((u >> 16) | 0x40u);
@@ -53,15 +58,22 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 // Grid barrier: workgroup w publishes how many barriers it has reached in its
 // own flag word (bar[w * kFlagStride]); wave 0 of every workgroup polls all W
 // flags (one lane per flag) until each has reached the target.  No
-// read-modify-write on a shared word, so arrivals do not serialise.  Every
-// thread fences its global writes (agent scope) before the arrival; the wait
-// has a give-up bound so a lost workgroup can never hang the device (the
-// error flag then stops every workgroup).  Arrival and wait are separate
-// calls so that work which reads nothing the other workgroups write can run
-// in between.
+// read-modify-write on a shared word, so arrivals do not serialise.  Each
+// wave waits until its own global writes have completed, the workgroup
+// synchronises, and thread 0 publishes them all with one agent-scope release
+// store (one L2 write-back per workgroup instead of one per wave); on the
+// other side the polling wave acquires once and the workgroup barrier hands
+// that on to the other waves.  The wait has a give-up bound so a lost
+// workgroup can never hang the device (the error flag then stops every
+// workgroup).  Arrival and wait are separate calls so that work which reads
+// nothing the other workgroups write can run in between.
 // ---------------------------------------------------------------------------
+// s_waitcnt operand (gfx9 encoding) that waits for vmcnt(0) only: vector memory
+// counter 0 (bits 3:0 and 15:14), export and LDS/scalar counters at their maxima.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 __device__ __forceinline__ void barrier_arrive(const ChainArgs& a, unsigned passed) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (threadIdx.x == 0)
     __hip_atomic_store(a.bar + blockIdx.x * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -91,7 +103,6 @@ __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed
     if (threadIdx.x == 0) *flag_lds = good;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *flag_lds != 0;
 }
 
@@ -106,8 +117,7 @@ struct LaneRec {
   int idx[NM];         // the N indices (only read at compile-time positions)
   float x;             // the value
   int rown;            // index in the phase's mode n
-  int rpm;             // index in the mode the previous phase updated (or -1)
-  int meta;            // run metadata (factor phases)
+  int meta;            // run metadata and split-row patch entry (see kMetaPatchShift)
   bool valid;
 };
 
@@ -122,7 +132,6 @@ __device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int N, int64_t
   for (int k = 0; k < NM; ++k) r.idx[k] = 0;
   r.x = 0.f;
   r.rown = 0;
-  r.rpm = -1;
   r.meta = 0;
   if (r.valid) {
     const uint32_t* src = (ph == 0) ? a.coo + (base + q) * a.s.R
@@ -132,8 +141,7 @@ __device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int N, int64_t
       if (k < N) r.idx[k] = (int)src[k];
     r.x = __uint_as_float(src[a.s.R - 1]);
     r.rown = (int)src[pt.n];
-    if (pt.pm >= 0) r.rpm = (int)src[pt.pm];
-    if (ph > 0) r.meta = a.meta[(int64_t)(ph - 1) * a.T + base + q];
+    r.meta = (int)a.meta[(int64_t)ph * a.T + base + q];
   }
 }
 
@@ -231,8 +239,11 @@ __device__ __forceinline__ void gather_rows(const ChainArgs& a, const int (&idx)
 // Finish the rows that straddled chunk boundaries in the previous factor
 // sub-step (mode pm).  xr[bw] is the straddling row at boundary bw or -1,
 // xn[bw] the entry number of a row's first boundary or -1 (both from the
-// schedule); cbuf holds the LDS copy of the carry slots [row, count, partial
-// sum (J), old master row (J)].  Fills the LDS table `split` (row, then the new
+// schedule); cbuf holds the LDS copy of the carry slots, element-major:
+// element e of slot sl at cbuf[e * 2W + sl], slot 2w the run that began
+// before chunk w, slot 2w+1 the run that goes on after it, elements [row,
+// count, partial sum (J), old master row (J)] (adjacent boundaries read
+// adjacent words).  Fills the LDS table `split` (row, then the new
 // master row at +4) in row order.  If `store`, also writes the rows (master,
 // and BF16 copy in BF16 mode).
 template <int JR, bool EXACT, bool BF>
@@ -244,17 +255,18 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
     const int e = xn[bw];
     if (e < 0) continue;
     const int row = xr[bw];
-    const float* slotB = cbuf + ((size_t)(bw - 1) * 2 + 1) * a.carry_stride;
+    const int NS = 2 * a.W;
+    const float* slotB = cbuf + (bw - 1) * 2 + 1;
     float F[JR];
-    int c = __float_as_int(slotB[1]);
+    int c = __float_as_int(slotB[NS]);
 #pragma unroll
-    for (int j = 0; j < JR; ++j) F[j] = (EXACT || j < pJ) ? slotB[2 + j] : 0.f;
+    for (int j = 0; j < JR; ++j) F[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
     for (int v = bw; v < a.W && xr[v] == row; ++v) {
-      const float* slotA = cbuf + ((size_t)v * 2 + 0) * a.carry_stride;
-      c += __float_as_int(slotA[1]);
+      const float* slotA = cbuf + v * 2;
+      c += __float_as_int(slotA[NS]);
 #pragma unroll
       for (int j = 0; j < JR; ++j)
-        if (EXACT || j < pJ) F[j] += slotA[2 + j];
+        if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
     }
     float* ent = split + e * sstride;
     ent[0] = __int_as_float(row);
@@ -262,7 +274,7 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
 #pragma unroll
     for (int j = 0; j < JR; ++j) {
       if (EXACT || j < pJ) {
-        const float old = slotB[2 + pJ + j];
+        const float old = slotB[(2 + pJ + j) * NS];
         ent[4 + j] = old - a.gA * (F[j] * inv_c + a.lA * old);
       }
     }
@@ -387,12 +399,78 @@ __device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, con
   }
 }
 
+// Segmented inclusive sum over the 64 lanes of a wave (fixed order): lane l
+// adds the values of lanes [ws, l), ws = the first lane of its segment
+// (ws <= l).  Within each row of 16 lanes by DPP row shifts (1, 2, 4, 8),
+// then across rows by the row broadcasts of lanes 15 and 31.
+template <int D>
+__device__ __forceinline__ float dpp_row_shr(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_bcast15(float v) {  // rows 1 and 3 get lanes 15 and 47, rows 0 and 2 get 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+}
+__device__ __forceinline__ float dpp_bcast31(float v) {  // rows 2 and 3 get lane 31, rows 0 and 1 get 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+}
+
+template <int JR, bool EXACT>
+__device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int lane, int ws) {
+  const int rl = lane & 15;
+  const bool t1 = rl >= 1 && lane - 1 >= ws, t2 = rl >= 2 && lane - 2 >= ws;
+  const bool t4 = rl >= 4 && lane - 4 >= ws, t8 = rl >= 8 && lane - 8 >= ws;
+  const int row = lane >> 4;
+  const bool t15 = (row & 1) && (lane | 15) - 16 >= ws;  // lane 16*row - 1
+  const bool t31 = row >= 2 && 31 >= ws;
+#pragma unroll
+  for (int j = 0; j < JR; ++j) {
+    if (EXACT || j < Jn) {
+      float v = u[j];
+      float o = dpp_row_shr<1>(v);
+      v += t1 ? o : 0.f;
+      o = dpp_row_shr<2>(v);
+      v += t2 ? o : 0.f;
+      o = dpp_row_shr<4>(v);
+      v += t4 ? o : 0.f;
+      o = dpp_row_shr<8>(v);
+      v += t8 ? o : 0.f;
+      o = dpp_bcast15(v);
+      v += t15 ? o : 0.f;
+      o = dpp_bcast31(v);
+      v += t31 ? o : 0.f;
+      u[j] = v;
+    }
+  }
+}
+
+// Where the products hp_p[h] are read from: the hp buffer (hp[h * chp + p]),
+// or, with a single remaining mode (three-mode tensors), that mode's rows in
+// the row buffer directly (hp_p[h] = rowbuf[p * rs + rs_hi + h]).
+template <bool HPV>
+struct HpRef {
+  const float* base;
+  int hs, ps;  // strides of h and p
+  __device__ __forceinline__ f32x4 quad(int p, int h) const {  // samples p .. p+3
+    if constexpr (!HPV) {
+      return *reinterpret_cast<const f32x4*>(base + h * hs + p);
+    } else {
+      f32x4 v;
+      v[0] = base[p * ps + h];
+      v[1] = base[(p + 1) * ps + h];
+      v[2] = base[(p + 2) * ps + h];
+      v[3] = base[(p + 3) * ps + h];
+      return v;
+    }
+  }
+  __device__ __forceinline__ float one(int p, int h) const { return base[h * hs + p * ps]; }
+};
+
 // E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
 // header).  Each wave carries two 16-sample tiles at once so that two
 // independent MFMA chains overlap.
-template <int JR, bool BF, bool EXACT>
-__device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf, const float* hp,
-                       int cnt, int chp, float* ebuf, int es) {
+template <int JR, bool BF, bool EXACT, bool HPV>
+__device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf,
+                                       const HpRef<HPV>& hpr, int cnt, int chp, float* ebuf, int es) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
@@ -410,8 +488,8 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
     const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
     const int prow0c = min(prow0, chp - 1), prow1c = min(prow1, chp - 1);
     f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
-    const float* hp0 = hp + mt0 * 16 + 4 * kq;
-    const float* hp1 = hp + min(mt1, MT - 1) * 16 + 4 * kq;  // (tile mt1 is masked when it does not exist)
+    const int hq0 = mt0 * 16 + 4 * kq;
+    const int hq1 = min(mt1, MT - 1) * 16 + 4 * kq;  // (a missing tile mt1 is never stored)
     if constexpr (!BF) {
       constexpr int KS = (JR + 3) / 4;
       float a0[KS], a1[KS];
@@ -441,10 +519,10 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bw, d1, 0, 0, 0);
           }
         }
-        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
-        const f32x4 g0 = *reinterpret_cast<const f32x4*>(hp0 + (h + 1) * chp);
-        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
-        const f32x4 g1 = *reinterpret_cast<const f32x4*>(hp1 + (h + 1) * chp);
+        const f32x4 h0 = hpr.quad(hq0, h);
+        const f32x4 g0 = hpr.quad(hq0, h + 1);
+        const f32x4 h1 = hpr.quad(hq1, h);
+        const f32x4 g1 = hpr.quad(hq1, h + 1);
         e0[0] = fmaf(c0[0], h0[0], e0[0]);
         e0[1] = fmaf(c0[1], h0[1], e0[1]);
         e0[2] = fmaf(c0[2], h0[2], e0[2]);
@@ -472,8 +550,8 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, c1, 0, 0, 0);
           }
         }
-        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
-        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
+        const f32x4 h0 = hpr.quad(hq0, h);
+        const f32x4 h1 = hpr.quad(hq1, h);
         e0[0] = fmaf(c0[0], h0[0], e0[0]);
         e0[1] = fmaf(c0[1], h0[1], e0[1]);
         e0[2] = fmaf(c0[2], h0[2], e0[2]);
@@ -508,8 +586,8 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
             c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
           }
         }
-        const f32x4 h0 = *reinterpret_cast<const f32x4*>(hp0 + h * chp);
-        const f32x4 h1 = *reinterpret_cast<const f32x4*>(hp1 + h * chp);
+        const f32x4 h0 = hpr.quad(hq0, h);
+        const f32x4 h1 = hpr.quad(hq1, h);
         e0[0] = fmaf(c0[0], h0[0], e0[0]);
         e0[1] = fmaf(c0[1], h0[1], e0[1]);
         e0[2] = fmaf(c0[2], h0[2], e0[2]);
@@ -535,9 +613,9 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 // p >= cnt).  Jobs are (h, j0 tile, j_lo tile); a wave carries up to three
 // jobs with the same tiles and consecutive h at once, which share the A row
 // and B column loads and keep three independent MFMA chains in flight.
-template <int JR, bool BF, bool EXACT>
-__device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra, int ras,
-                               const float* hp, int cnt, int chp, float* out) {
+template <int JR, bool BF, bool EXACT, bool HPV>
+__device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra,
+                                               int ras, const HpRef<HPV>& hpr, int cnt, int chp, float* out) {
   constexpr int JG = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -558,12 +636,12 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
     const int jl = 16 * t1 + r16;  // B column
     const bool bcol = jl < jlo;
     const int h0 = hg * JG;
-    const float* hph[JG];
+    int hh[JG];
     bool hok[JG];
 #pragma unroll
     for (int q = 0; q < JG; ++q) {
       hok[q] = h0 + q < khi;
-      hph[q] = hp + (hok[q] ? h0 + q : h0) * chp;
+      hh[q] = hok[q] ? h0 + q : h0;
     }
     f32x4 c[JG];
 #pragma unroll
@@ -579,7 +657,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
         rav = ra[p * ras + j0];
         bv = rowbuf[p * s.rs + lo_off + jl];
 #pragma unroll
-        for (int q = 0; q < JG; ++q) hv[q] = hph[q][p];
+        for (int q = 0; q < JG; ++q) hv[q] = hpr.one(p, hh[q]);
       };
       float rav, bv, hv[JG];
       if (nsteps > 0) load(0, rav, bv, hv);
@@ -611,7 +689,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int p = st * 16 + 4 * kq + e;
-            av[e] = (short)bf16_bits(rav[e] * hph[q][p]);
+            av[e] = (short)bf16_bits(rav[e] * hpr.one(p, hh[q]));
           }
           c[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c[q], 0, 0, 0);
         }
@@ -666,7 +744,8 @@ __device__ __forceinline__ void copy_carry(const ChainArgs& a, int par, float* c
 //   table; workgroup 0 stores it; until the next barrier nobody else reads it
 //   from global memory, and the rows of that mode are read after the barrier
 //   that follows).
-// Carry slot: [0] row, [1] count, [2, 2+J) partial sum, [2+J, 2+2J) old row.
+// Carry slot elements: [0] row, [1] count, [2, 2+J) partial sum, [2+J, 2+2J)
+// old row; stored element-major (element e of slot sl at e * 2W + sl).
 // ---------------------------------------------------------------------------
 template <int JU, int NU, int BFI>
 __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
@@ -713,7 +792,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 
   // ---- set-up: core, index maps, resident tables
   for (int lin = tid; lin < P; lin += BT) Gs[lin] = a.G[lin];
-  for (int i = tid; i < chp * s.rs; i += BT) rowbuf[i] = 0.f;
+  // (plus a zero tail: the MFMA K steps read up to 31 words past a row)
+  for (int i = tid; i < chp * s.rs + kRowTail; i += BT) rowbuf[i] = 0.f;
   for (int i = tid; i < L.aux_len; i += BT) {
     const int v = a.aux[i];
     if (i < L.hm_len) hmap[i] = v;
@@ -850,24 +930,17 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       if (splits) {
         const int nsplit = misc[0];
         finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
-        if (active && nsplit > 0) {
-          // the table follows the chunk boundaries, so its rows are increasing
+        // the schedule says which entry (if any) holds this sample's mode-pm row
+        const int pe = (cur.meta >> kMetaPatchShift) & 0xFF;
+        if (active && pe > 0) {
           const int pJ = EXACT ? JR : s.J[pm];
-          const int prow = cur.rpm;
-          int lo2 = 0, hi2 = nsplit;
-          while (lo2 < hi2) {
-            const int mid = (lo2 + hi2) >> 1;
-            if (__float_as_int(split[mid * sstride]) < prow) lo2 = mid + 1;
-            else hi2 = mid;
-          }
-          if (lo2 < nsplit && __float_as_int(split[lo2 * sstride]) == prow) {
-            float* dst = rb + s.rs_off[pm];
+          const float* ent = split + (pe - 1) * sstride + 4;
+          float* dst = rb + s.rs_off[pm];
 #pragma unroll
-            for (int j = 0; j < JR; ++j) {
-              if (EXACT || j < pJ) {
-                const float v = split[lo2 * sstride + 4 + j];
-                dst[j] = BF ? bf16_round(v) : v;
-              }
+          for (int j = 0; j < JR; ++j) {
+            if (EXACT || j < pJ) {
+              const float v = ent[j];
+              dst[j] = BF ? bf16_round(v) : v;
             }
           }
         }
@@ -886,10 +959,17 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       }
 
       // ---- 5. E_p for every sample of the chunk
-      build_hp(s, pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
+      constexpr bool HPV = NU == 3;  // one remaining mode: hp is a view of its rows
+      HpRef<HPV> hpr;
+      if constexpr (HPV) {
+        hpr = HpRef<HPV>{rowbuf + pt.rs_hi, 1, s.rs};
+      } else {
+        build_hp(s, pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
+        hpr = HpRef<HPV>{hp, chp, 1};
+      }
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
-      mfma_E<JR, BF, EXACT>(s, pt, TBn, rowbuf, hp, cnt, chp, ebuf, es);
+      mfma_E<JR, BF, EXACT, HPV>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
       __syncthreads();
 
       if (ph == 0) {
@@ -909,7 +989,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
         __syncthreads();
         // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
-        mfma_core_grad<JR, BF, EXACT>(s, pt, rowbuf, rabuf, ras, hp, cnt, chp, a.partial + (size_t)w * Pp);
+        mfma_core_grad<JR, BF, EXACT, HPV>(s, pt, rowbuf, rabuf, ras, hpr, cnt, chp, a.partial + (size_t)w * Pp);
       } else {
         // ================= mode-n sub-step =================
         float u[JR], an[JR];
@@ -938,16 +1018,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         const int meta = cur.meta;
         const int sf = meta & 511;
         const int wstart = max(sf, wv * 64) - wv * 64;
-        for (int d = 1; d < 64; d <<= 1) {
-          const bool take = (lane - d) >= wstart;
-#pragma unroll
-          for (int j = 0; j < JR; ++j) {
-            if (EXACT || j < Jn) {
-              const float o = __shfl_up(u[j], d);
-              if (take) u[j] += o;
-            }
-          }
-        }
+        wave_segmented_scan<JR, EXACT>(u, Jn, lane, wstart);
         if (lane == 63) {
 #pragma unroll
           for (int j = 0; j < JR; ++j)
@@ -978,14 +1049,16 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
               }
             }
           } else {
-            float* slot = a.carry + (size_t)par * carry_par_stride + ((size_t)w * 2 + (before ? 0 : 1)) * a.carry_stride;
+            // element-major carry slots (element e of slot sl at e * 2W + sl)
+            const int NS = 2 * a.W;
+            float* slot = a.carry + (size_t)par * carry_par_stride + (size_t)w * 2 + (before ? 0 : 1);
             slot[0] = __int_as_float(row);
-            slot[1] = __int_as_float(c);
+            slot[NS] = __int_as_float(c);
 #pragma unroll
             for (int j = 0; j < JR; ++j) {
               if (EXACT || j < Jn) {
-                slot[2 + j] = u[j];
-                slot[2 + Jn + j] = an[j];
+                slot[(size_t)(2 + j) * NS] = u[j];
+                slot[(size_t)(2 + Jn + j) * NS] = an[j];
               }
             }
           }
@@ -1033,6 +1106,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 // Host side: the LDS plan, the per-phase constants and the index maps.
 // ---------------------------------------------------------------------------
 size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
+  // the row buffer is followed by kRowTail zero words (see k_chain)
   const Shape& s = a.s;
   // every region below is sized from these: refuse an incomplete request
   if (a.W < 1 || a.chunk < 1 || a.chunk > threads || (a.W > 1 && (a.carry_stride < 4 || a.split_cap < a.W - 1)))
@@ -1076,7 +1150,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.ras = pad4(JR) + 1;
   L.sstride = 4 + pad4(JR);
   L.wstride = pad4(JR) + 4;
-  size_t common = al(s.P) + al((size_t)L.chp * s.rs) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
+  size_t common = al(s.P) + al((size_t)L.chp * s.rs + kRowTail) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
                   al((size_t)L.chp * L.ras) + al((size_t)a.split_cap * L.sstride) +
                   al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0) + al((size_t)hm_len) +
                   al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
@@ -1085,7 +1159,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   size_t off = 0;
   L.gs = (int)off;    off += al(s.P);
   L.tb = (int)off;    off += al(L.tb_all ? tbf(tb_sum) : tbf(tb_max));
-  L.row = (int)off;   off += al((size_t)L.chp * s.rs);
+  L.row = (int)off;   off += al((size_t)L.chp * s.rs + kRowTail);
   L.hp = (int)off;    off += al((size_t)khimax * L.chp);
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras);
@@ -1120,6 +1194,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     t.rs_lo = s.rs_off[q.lo];
     t.rs_n = s.rs_off[n];
     t.Jn = s.J[n];
+    t.rs_hi = q.nhi > 0 ? s.rs_off[q.hi[0]] : 0;
     t.tb_off = L.tb_all ? q.tb_off : 0;
     t.tb_len = q.tb_len;
     t.hm_off = q.hm_off;

@@ -52,6 +52,7 @@ struct PhaseTab {
   int khi, nhi;  // product and count of the modes other than n and lo
   int jlo, kp, nt;
   int ls_n, ls_lo, rs_lo, rs_n, Jn;
+  int rs_hi;     // row-buffer offset of the first remaining mode (0 if none)
   int tb_off;    // element offset of mode n's table in the table region
   int tb_len;    // elements of mode n's table
   int hm_off;    // int offset of mode n's row-offset map
@@ -63,11 +64,16 @@ struct PhaseTab {
 // first boundary or -1, [2W] number of straddling rows.
 __host__ __device__ inline int xrow_stride(int W) { return 2 * W + 4; }
 
-// Run metadata of a sorted position (16 bits): bits 0-8 the chunk-local
-// position where its row's run starts in the chunk, bit 9 last position of
-// the run in the chunk, bit 10 run began in an earlier chunk, bit 11 run goes
-// on in the next chunk.
+// Per-position metadata of every phase ([N+1][T] words; phase 0 is the core
+// sub-step in minibatch order, phase n+1 the (row, position) order of mode n).
+// Factor phases: bits 0-8 the chunk-local position where the row's run
+// starts in the chunk, bit 9 last position of the run in the chunk, bit 10
+// run began in an earlier chunk, bit 11 run goes on in the next chunk.
+// All phases: bits 16-23 hold 1 + the entry of the previous phase's table of
+// straddling rows that holds this position's row of the mode that phase
+// updated (0: none).
 constexpr int kMetaTail = 1 << 9, kMetaBefore = 1 << 10, kMetaAfter = 1 << 11;
+constexpr int kMetaPatchShift = 16;
 
 // Arguments of the persistent minibatch chain kernel.
 struct ChainArgs {
@@ -76,7 +82,7 @@ struct ChainArgs {
   const uint16_t* sigma;    // [N][T] per-minibatch sorted positions
   const uint32_t* rec_sorted; // [N][T] records in (row, position) order per minibatch
   const int* xrow;          // [nb][N][xrow_stride(W)] chunk-boundary rows and their numbering
-  const uint16_t* meta;     // [N][T] run metadata of each sorted position
+  const uint32_t* meta;     // [N+1][T] per-position metadata of every phase
   const int* aux;           // host-built maps (lay.aux_len ints)
   float* A[kMaxOrder];      // FP32 master factors, I_n x Jp_n
   uint16_t* Ab[kMaxOrder];  // BF16 read copies (null in FP32 mode), I_n x Jb_n
@@ -108,7 +114,7 @@ hipError_t launch_perm_gather(const Shape& s, const uint32_t* coo, uint32_t* coo
                               uint64_t seed, int64_t epoch, hipStream_t st);
 hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, hipStream_t st);
 hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg,
-                       uint32_t* rec_sorted, uint16_t* meta, int W, int chunk, int64_t T, int64_t M,
+                       uint32_t* rec_sorted, uint32_t* meta, int W, int chunk, int64_t T, int64_t M,
                        int64_t b_begin, int64_t b_end, hipStream_t st);
 hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const uint16_t* sigma,
                                  int64_t T, int64_t M, int64_t b, int mode, int32_t* seg_off,

@@ -40,7 +40,7 @@ struct stdecomp_handle {
   uint32_t* rec_sorted = nullptr;
   int* xrow = nullptr;
   int* nseg = nullptr;
-  uint16_t* meta = nullptr;
+  uint32_t* meta = nullptr;
   int* aux = nullptr;
   float* A[kMaxOrder] = {};
   uint16_t* Ab[kMaxOrder] = {};  // BF16 read copies (BF16 mode)
@@ -458,7 +458,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   if ((rc = dalloc(h, &h->coo, T * s.R)) || (rc = dalloc(h, &h->coo_perm, T * s.R)) ||
       (rc = dalloc(h, &h->sigma, T * N)) || (rc = dalloc(h, &h->rec_sorted, T * N * s.R)) ||
       (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * stdk::xrow_stride(h->W))) ||
-      (rc = dalloc(h, &h->meta, T * N)) || (rc = dalloc(h, &h->aux, h->aux_host.size())) ||
+      (rc = dalloc(h, &h->meta, T * (N + 1))) || (rc = dalloc(h, &h->aux, h->aux_host.size())) ||
       (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
       (rc = dalloc(h, &h->partial, (size_t)h->W * stdk::pad4((int)P))) ||
       (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||

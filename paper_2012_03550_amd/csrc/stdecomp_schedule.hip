@@ -98,7 +98,7 @@ hipError_t launch_perm_only(int64_t T, uint64_t seed, int64_t epoch, int64_t* ou
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restrict__ coo, uint16_t* __restrict__ sigma,
                                                        int* __restrict__ xrow, int* __restrict__ nseg,
-                                                       uint32_t* __restrict__ rec_sorted, uint16_t* __restrict__ meta,
+                                                       uint32_t* __restrict__ rec_sorted, uint32_t* __restrict__ meta,
                                                        int64_t T, int64_t M, int64_t b_begin, int R, int N, int W,
                                                        int chunk) {
   extern __shared__ unsigned long long keys[];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restric
     int st = __shfl_up(incl, 1);
     if (lane == 0) st = -1;
     for (int v = 0; v < wv; ++v) st = max(st, wtot[v]);
-    uint16_t* mt = meta + (int64_t)n * T + base;
+    uint32_t* mt = meta + (int64_t)(n + 1) * T + base;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int pos = out0 + i;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restric
         if (!next_same || chunk_end) v |= kMetaTail;
         if (sf == 0 && st < qlo) v |= kMetaBefore;
         if (chunk_end && next_same) v |= kMetaAfter;
-        mt[pos] = (uint16_t)v;
+        mt[pos] = (uint32_t)v;
       }
     }
   }
@@ -248,8 +248,57 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const uint32_t* __restric
   }
 }
 
+// Which entry of the previous phase's straddling-row table patches each
+// position: phase ph finishes the rows of mode pm (updated by the phase
+// before it) that straddled chunk boundaries; a position whose mode-pm row is
+// one of them gets 1 + its entry number in bits 16-23 of its metadata word.
+// One block per (minibatch, phase); runs after the sort of every mode.
+__global__ __launch_bounds__(kSortThreads) void k_patch(const uint32_t* __restrict__ coo,
+                                                        const uint32_t* __restrict__ rec_sorted,
+                                                        const int* __restrict__ xrow, uint32_t* __restrict__ meta,
+                                                        int64_t T, int64_t M, int64_t b_begin, int R, int N, int W) {
+  __shared__ int ent_row[1024];
+  __shared__ int nent;
+  const int64_t b = b_begin + blockIdx.x;
+  const int ph = blockIdx.y;
+  const int64_t base = b * M;
+  const int m = (int)((T - base < M) ? (T - base) : M);
+  const int pm = ph == 0 ? N - 1 : ph - 2;  // phase 1 follows the core sub-step: nothing to finish
+  const int64_t bp = ph == 0 ? b - 1 : b;
+  const bool any = W > 1 && pm >= 0 && bp >= 0;
+  if (threadIdx.x == 0) nent = 0;
+  __syncthreads();
+  if (any) {
+    const int* xr = xrow + ((size_t)bp * N + pm) * xrow_stride(W);
+    for (int bw = threadIdx.x; bw < W; bw += kSortThreads) {
+      const int e = xr[W + bw];
+      if (e >= 0 && e < 1024) ent_row[e] = xr[bw];
+    }
+    if (threadIdx.x == 0) nent = min(xr[2 * W], 1024);
+  }
+  __syncthreads();
+  const int ne = nent;
+  uint32_t* mt = meta + (int64_t)ph * T + base;
+  for (int q = threadIdx.x; q < m; q += kSortThreads) {
+    int code = 0;
+    if (ne > 0) {
+      const uint32_t* rec = ph == 0 ? coo + (base + q) * R : rec_sorted + ((int64_t)(ph - 1) * T + base + q) * R;
+      const int row = (int)rec[pm];
+      int lo = 0, hi = ne;  // entries follow the boundaries, so their rows increase
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ent_row[mid] < row) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < ne && ent_row[lo] == row) code = (lo + 1) << kMetaPatchShift;
+    }
+    if (ph == 0) mt[q] = (uint32_t)code;  // the core phase has no run metadata
+    else if (ph >= 2) mt[q] |= (uint32_t)code;
+  }
+}
+
 hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma, int* xrow, int* nseg,
-                       uint32_t* rec_sorted, uint16_t* meta, int W, int chunk, int64_t T, int64_t M,
+                       uint32_t* rec_sorted, uint32_t* meta, int W, int chunk, int64_t T, int64_t M,
                        int64_t b_begin, int64_t b_end, hipStream_t st) {
   const int64_t nb = b_end - b_begin;
   if (nb <= 0) return hipSuccess;
@@ -265,6 +314,14 @@ hipError_t launch_sort(const Shape& s, const uint32_t* coo_perm, uint16_t* sigma
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_sort<64>, grid, dim3(kSortThreads), 16384 * 8, st, coo_perm, sigma, xrow, nseg, rec_sorted, meta, T, M, b_begin + b0, s.R, s.N, W, chunk);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (s.N + 1 > 65535) return hipErrorInvalidValue;
+  for (int64_t b0 = 0; b0 < nb; b0 += 65535) {
+    const int g = (int)((nb - b0 < 65535) ? nb - b0 : 65535);
+    hipLaunchKernelGGL(k_patch, dim3(g, s.N + 1), dim3(kSortThreads), 0, st, coo_perm, rec_sorted, xrow, meta, T, M,
+                       b_begin + b0, s.R, s.N, W);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
