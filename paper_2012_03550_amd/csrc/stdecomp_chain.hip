@@ -268,16 +268,17 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
       for (int j = 0; j < JR; ++j)
         if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
     }
+    // (every LDS read before the first write: the compiler cannot tell the
+    // table from the slots and would otherwise order each read after it)
+    float old[JR];
+#pragma unroll
+    for (int j = 0; j < JR; ++j) old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
     float* ent = split + e * sstride;
     ent[0] = __int_as_float(row);
     const float inv_c = 1.0f / (float)c;
 #pragma unroll
-    for (int j = 0; j < JR; ++j) {
-      if (EXACT || j < pJ) {
-        const float old = slotB[(2 + pJ + j) * NS];
-        ent[4 + j] = old - a.gA * (F[j] * inv_c + a.lA * old);
-      }
-    }
+    for (int j = 0; j < JR; ++j)
+      if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * (F[j] * inv_c + a.lA * old[j]);
   }
   __syncthreads();
   if (store) {
@@ -468,7 +469,7 @@ struct HpRef {
 // E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
 // header).  Each wave carries two 16-sample tiles at once so that two
 // independent MFMA chains overlap.
-template <int JR, bool BF, bool EXACT, bool HPV>
+template <int JR, bool BF, bool EXACT, bool HPV, int KHI>
 __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf,
                                        const HpRef<HPV>& hpr, int cnt, int chp, float* ebuf, int es) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -501,66 +502,32 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
         a0[ks] = rowbuf[prow0c * s.rs + lo_off + k];
         a1[ks] = rowbuf[prow1c * s.rs + lo_off + k];
       }
+      // One accumulation chain per tile over K = (j_lo, h): the A operand is
+      // a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
+      // stage folds into the MFMA chain.
       const int nks = kp >> 2;
       const float* tb = TB + (t * kp + kq) * 16 + r16;
       const int hstride = nt * kp * 16;
-      int h = 0;
-      for (; h + 1 < khi; h += 2) {  // two h per iteration: four independent MFMA chains
-        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-        f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+      auto step = [&](int h) {
+        const float hv0 = hpr.one(prow0c, h), hv1 = hpr.one(prow1c, h);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           if (ks < nks) {
             const float bv = tb[h * hstride + ks * 64];
-            const float bw = tb[(h + 1) * hstride + ks * 64];
-            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, c1, 0, 0, 0);
-            d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bw, d0, 0, 0, 0);
-            d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bw, d1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, c1, 0, 0, 0);
           }
         }
-        const f32x4 h0 = hpr.quad(hq0, h);
-        const f32x4 g0 = hpr.quad(hq0, h + 1);
-        const f32x4 h1 = hpr.quad(hq1, h);
-        const f32x4 g1 = hpr.quad(hq1, h + 1);
-        e0[0] = fmaf(c0[0], h0[0], e0[0]);
-        e0[1] = fmaf(c0[1], h0[1], e0[1]);
-        e0[2] = fmaf(c0[2], h0[2], e0[2]);
-        e0[3] = fmaf(c0[3], h0[3], e0[3]);
-        e1[0] = fmaf(c1[0], h1[0], e1[0]);
-        e1[1] = fmaf(c1[1], h1[1], e1[1]);
-        e1[2] = fmaf(c1[2], h1[2], e1[2]);
-        e1[3] = fmaf(c1[3], h1[3], e1[3]);
-        e0[0] = fmaf(d0[0], g0[0], e0[0]);
-        e0[1] = fmaf(d0[1], g0[1], e0[1]);
-        e0[2] = fmaf(d0[2], g0[2], e0[2]);
-        e0[3] = fmaf(d0[3], g0[3], e0[3]);
-        e1[0] = fmaf(d1[0], g1[0], e1[0]);
-        e1[1] = fmaf(d1[1], g1[1], e1[1]);
-        e1[2] = fmaf(d1[2], g1[2], e1[2]);
-        e1[3] = fmaf(d1[3], g1[3], e1[3]);
-      }
-      for (; h < khi; ++h) {
-        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+      };
+      if constexpr (KHI > 0) {  // trip count known: straight-line code, loads scheduled early
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (ks < nks) {
-            const float bv = tb[h * hstride + ks * 64];
-            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], bv, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], bv, c1, 0, 0, 0);
-          }
-        }
-        const f32x4 h0 = hpr.quad(hq0, h);
-        const f32x4 h1 = hpr.quad(hq1, h);
-        e0[0] = fmaf(c0[0], h0[0], e0[0]);
-        e0[1] = fmaf(c0[1], h0[1], e0[1]);
-        e0[2] = fmaf(c0[2], h0[2], e0[2]);
-        e0[3] = fmaf(c0[3], h0[3], e0[3]);
-        e1[0] = fmaf(c1[0], h1[0], e1[0]);
-        e1[1] = fmaf(c1[1], h1[1], e1[1]);
-        e1[2] = fmaf(c1[2], h1[2], e1[2]);
-        e1[3] = fmaf(c1[3], h1[3], e1[3]);
+        for (int h = 0; h < KHI; ++h) step(h);
+      } else {
+        for (int h = 0; h < khi; ++h) step(h);
       }
+      e0 = c0;
+      e1 = c1;
     } else {
       constexpr int KS = (JR + 15) / 16;
       s16x4 a0[KS], a1[KS];
@@ -647,31 +614,40 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
 #pragma unroll
     for (int q = 0; q < JG; ++q) c[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF) {
-      // Operands of step st+1 are read before the MFMAs of step st.  No
-      // masks: p < chp always (4 * nsteps <= chp); positions p >= cnt have
-      // zero r a(0) and zero hp, and the row buffer holds finite values
-      // only; rows j0 >= J0 and columns jl >= J_lo reach only outputs that
-      // are not stored.
-      auto load = [&](int st, float& rav, float& bv, float (&hv)[JG]) {
-        const int p = st * 4 + kq;
-        rav = ra[p * ras + j0];
-        bv = rowbuf[p * s.rs + lo_off + jl];
+      // K in groups of four steps (16 samples; 16 * groups <= chp), the
+      // operands of group g+1 read before the MFMAs of group g.  No masks:
+      // positions p >= cnt have zero r a(0) (and zero hp), the row buffer
+      // holds finite values only; rows j0 >= J0 and columns jl >= J_lo
+      // reach only outputs that are not stored.
+      const int ngroups = (nsteps + 3) >> 2;
+      auto load = [&](int gi, float (&rav)[4], float (&bv)[4], float (&hv)[4][JG]) {
 #pragma unroll
-        for (int q = 0; q < JG; ++q) hv[q] = hpr.one(p, hh[q]);
+        for (int u = 0; u < 4; ++u) {
+          const int p = (4 * gi + u) * 4 + kq;
+          rav[u] = ra[p * ras + j0];
+          bv[u] = rowbuf[p * s.rs + lo_off + jl];
+#pragma unroll
+          for (int q = 0; q < JG; ++q) hv[u][q] = hpr.one(p, hh[q]);
+        }
       };
-      float rav, bv, hv[JG];
-      if (nsteps > 0) load(0, rav, bv, hv);
-      for (int st = 0; st < nsteps; ++st) {
-        float rav2 = 0.f, bv2 = 0.f, hv2[JG];
+      float rav[4], bv[4], hv[4][JG];
+      if (ngroups > 0) load(0, rav, bv, hv);
+      for (int gi = 0; gi < ngroups; ++gi) {
+        float rn[4], bn[4], hn[4][JG];
+        load(gi + 1 < ngroups ? gi + 1 : gi, rn, bn, hn);
 #pragma unroll
-        for (int q = 0; q < JG; ++q) hv2[q] = 0.f;
-        if (st + 1 < nsteps) load(st + 1, rav2, bv2, hv2);
+        for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int q = 0; q < JG; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rav * hv[q], bv, c[q], 0, 0, 0);
-        rav = rav2;
-        bv = bv2;
+          for (int q = 0; q < JG; ++q)
+            c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rav[u] * hv[u][q], bv[u], c[q], 0, 0, 0);
+        }
 #pragma unroll
-        for (int q = 0; q < JG; ++q) hv[q] = hv2[q];
+        for (int u = 0; u < 4; ++u) {
+          rav[u] = rn[u];
+          bv[u] = bn[u];
+#pragma unroll
+          for (int q = 0; q < JG; ++q) hv[u][q] = hn[u][q];
+        }
       }
     } else {
       for (int st = 0; st < nsteps; ++st) {
@@ -911,14 +887,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
             for (int u = 0; u < 16; ++u)
               if (vb + u < a.W) sum += t[u];
           }
+          float gv[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int lin = 4 * l4 + i;
-            if (lin < P) {
-              const float gv = Gs[lin];
-              Gs[lin] = gv - a.gG * (-sum[i] * inv_m + a.lG * gv);
-            }
-          }
+          for (int i = 0; i < 4; ++i) gv[i] = Gs[min(4 * l4 + i, P - 1)];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (4 * l4 + i < P) Gs[4 * l4 + i] = gv[i] - a.gG * (-sum[i] * inv_m + a.lG * gv[i]);
         }
         __syncthreads();
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
@@ -936,13 +910,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           const int pJ = EXACT ? JR : s.J[pm];
           const float* ent = split + (pe - 1) * sstride + 4;
           float* dst = rb + s.rs_off[pm];
+          float v[JR];
 #pragma unroll
-          for (int j = 0; j < JR; ++j) {
-            if (EXACT || j < pJ) {
-              const float v = ent[j];
-              dst[j] = BF ? bf16_round(v) : v;
-            }
-          }
+          for (int j = 0; j < JR; ++j) v[j] = (EXACT || j < pJ) ? ent[j] : 0.f;
+#pragma unroll
+          for (int j = 0; j < JR; ++j)
+            if (EXACT || j < pJ) dst[j] = BF ? bf16_round(v[j]) : v[j];
         }
       }
 
@@ -969,23 +942,25 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       }
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
-      mfma_E<JR, BF, EXACT, HPV>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+      mfma_E<JR, BF, EXACT, HPV, (EXACT && NU == 3) ? JR : 0>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
       __syncthreads();
 
       if (ph == 0) {
         // ================= core sub-step =================
         if (tid < chp) {
-          float r = 0.f;
+          float r = 0.f, a0r[JR];
+#pragma unroll
+          for (int j = 0; j < JR; ++j) a0r[j] = (EXACT || j < Jn) ? rb[j] : 0.f;  // mode 0's row sits at offset 0
           if (active) {
             float xh = 0.f;
 #pragma unroll
             for (int j = 0; j < JR; ++j)
-              if (EXACT || j < Jn) xh = fmaf(rb[j], ebuf[tid * es + j], xh);  // mode 0's row sits at offset 0
+              if (EXACT || j < Jn) xh = fmaf(a0r[j], ebuf[tid * es + j], xh);
             r = cur.x - xh;
           }
 #pragma unroll
           for (int j = 0; j < JR; ++j)
-            if (EXACT || j < Jn) rabuf[tid * ras + j] = active ? r * rb[j] : 0.f;
+            if (EXACT || j < Jn) rabuf[tid * ras + j] = active ? r * a0r[j] : 0.f;
         }
         __syncthreads();
         // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
