@@ -146,92 +146,87 @@ __device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int N, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Factor rows of one sample held in registers: slot i is mode K0 + i, as raw
-// 16-byte vectors of the read copy (4 FP32 or 8 BF16 values).
+// Row buffers.  Chunk-major: mode k's values [c*V, c*V + V) (one 16-byte chunk;
+// V = 4 FP32 or 8 BF16 values of the read copy) of sample p sit at float word
+// ((coff[k] + c) * chp + p) * 4, so the 64 lanes of a wave (samples 64 wv + l)
+// fill 1 KB of consecutive LDS with one 16-byte transfer each.  The loads go
+// from global memory straight into LDS: no registers are held while they are
+// in flight, and a wave waits for vmcnt before the rows are read.
 // ---------------------------------------------------------------------------
-template <int JR, bool BF, int NS>
-struct RowRegs {
-  static constexpr int C = BF ? (JR + 7) / 8 : (JR + 3) / 4;
-  u32x4 v[NS > 0 ? NS : 1][C];
-};
-
-// (EXACT: every J_k equals JR, so the row lengths are compile-time constants)
-template <int JR, bool BF, bool EXACT, int NM, int NS, int K0>
-__device__ __forceinline__ void issue_rows(const ChainArgs& a, const int (&idx)[NM], unsigned mask,
-                                           RowRegs<JR, BF, NS>& rr) {
-  constexpr int C = RowRegs<JR, BF, NS>::C;
-  constexpr int PER = BF ? 8 : 4;
+template <int JR, bool BF, bool EXACT, int NM>
+__device__ __forceinline__ void issue_rows_lds(const ChainArgs& a, const int (&idx)[NM], unsigned mask, float* buf,
+                                               int chp, bool valid) {
+  constexpr int V = BF ? 8 : 4;
+  constexpr int CM = (JR + V - 1) / V;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const int k = K0 + i;
-    if (k < NM && ((mask >> k) & 1u)) {
-      const u32x4* src = BF ? reinterpret_cast<const u32x4*>(a.Ab[k] + (int64_t)idx[k] * a.Jb[k])
-                            : reinterpret_cast<const u32x4*>(a.A[k] + (int64_t)idx[k] * a.s.Jp[k]);
+  for (int k = 0; k < NM; ++k) {
+    if ((mask >> k) & 1u) {
+      const int J = EXACT ? JR : a.s.J[k];
+      const char* src = BF ? reinterpret_cast<const char*>(a.Ab[k] + (int64_t)idx[k] * a.Jb[k])
+                           : reinterpret_cast<const char*>(a.A[k] + (int64_t)idx[k] * a.s.Jp[k]);
+      float* dst = buf + (a.lay.coff[k] * chp + wv * 64) * 4;
 #pragma unroll
-      for (int c = 0; c < C; ++c)
-        if (EXACT || PER * c < a.s.J[k]) rr.v[i][c] = src[c];
+      for (int c = 0; c < CM; ++c)
+        if ((EXACT || c * V < J) && valid) __builtin_amdgcn_global_load_lds(src + 16 * c, dst + c * chp * 4, 16, 0, 0);
     }
   }
 }
 
-template <int JR, bool BF, bool EXACT, int NM, int NS, int K0>
-__device__ __forceinline__ void store_rows(const ChainArgs& a, unsigned mask, const RowRegs<JR, BF, NS>& rr,
-                                           float* rb) {
-  constexpr int C = RowRegs<JR, BF, NS>::C;
+// Value j of the mode whose chunks start at ck, for sample p.
+template <bool BF>
+__device__ __forceinline__ float row_at(const float* buf, int ck, int chp, int p, int j) {
+  if constexpr (!BF) {
+    return buf[((ck + (j >> 2)) * chp + p) * 4 + (j & 3)];
+  } else {
+    const unsigned short* b16 = reinterpret_cast<const unsigned short*>(buf);
+    return bf16_val(b16[((ck + (j >> 3)) * chp + p) * 8 + (j & 7)]);
+  }
+}
+
+// Sample p's whole row of a mode (values j >= J read as the zero padding of
+// the factor rows, or stay 0).
+template <int JR, bool BF, bool EXACT>
+__device__ __forceinline__ void read_row(const float* buf, int ck, int chp, int p, int J, float (&v)[JR]) {
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const int k = K0 + i;
-    if (k < NM && ((mask >> k) & 1u)) {
-      const int J = EXACT ? JR : a.s.J[k];
-      float* dst = rb + a.s.rs_off[k];
+  for (int j = 0; j < JR; ++j) v[j] = 0.f;
+  if constexpr (!BF) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const u32x4 w4 = rr.v[i][c];
-        if constexpr (!BF) {
+    for (int c = 0; c < (JR + 3) / 4; ++c) {
+      if (EXACT || 4 * c < J) {
+        const f32x4 t = *reinterpret_cast<const f32x4*>(buf + ((ck + c) * chp + p) * 4);
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (4 * c + e < J) dst[4 * c + e] = __uint_as_float(w4[e]);
-        } else {
+        for (int e = 0; e < 4; ++e)
+          if (4 * c + e < JR) v[4 * c + e] = t[e];
+      }
+    }
+  } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int j = 8 * c + e;
-            if (j < J) dst[j] = bf16_val((unsigned short)((e & 1) ? (w4[e >> 1] >> 16) : (w4[e >> 1] & 0xFFFFu)));
-          }
-        }
+    for (int c = 0; c < (JR + 7) / 8; ++c) {
+      if (EXACT || 8 * c < J) {
+        const u32x4 t = *reinterpret_cast<const u32x4*>(buf + ((ck + c) * chp + p) * 4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (8 * c + e < JR)
+            v[8 * c + e] = bf16_val((unsigned short)((e & 1) ? (t[e >> 1] >> 16) : (t[e >> 1] & 0xFFFFu)));
       }
     }
   }
 }
 
-// All rows of `mask` for one sample into its LDS row buffer, staged so that
-// at most 16 vectors are in registers at once.
-template <int JR, bool BF, bool EXACT, int NM>
-__device__ __forceinline__ void gather_rows(const ChainArgs& a, const int (&idx)[NM], unsigned mask, float* rb) {
-  constexpr int C = RowRegs<JR, BF, 1>::C;
-  constexpr int SP = (16 / C) < NM ? (16 / C) : NM;
-  static_assert(4 * SP >= NM, "four stages cover every mode");
-  RowRegs<JR, BF, SP> r0;
-  issue_rows<JR, BF, EXACT, NM, SP, 0>(a, idx, mask, r0);
-  store_rows<JR, BF, EXACT, NM, SP, 0>(a, mask, r0, rb);
-  if constexpr (SP < NM) {
-    if (mask >> SP) {
-      RowRegs<JR, BF, SP> r1;
-      issue_rows<JR, BF, EXACT, NM, SP, SP>(a, idx, mask, r1);
-      store_rows<JR, BF, EXACT, NM, SP, SP>(a, mask, r1, rb);
-    }
-  }
-  if constexpr (2 * SP < NM) {
-    if (mask >> (2 * SP)) {
-      RowRegs<JR, BF, SP> r2;
-      issue_rows<JR, BF, EXACT, NM, SP, 2 * SP>(a, idx, mask, r2);
-      store_rows<JR, BF, EXACT, NM, SP, 2 * SP>(a, mask, r2, rb);
-    }
-  }
-  if constexpr (3 * SP < NM) {
-    if (mask >> (3 * SP)) {
-      RowRegs<JR, BF, SP> r3;
-      issue_rows<JR, BF, EXACT, NM, SP, 3 * SP>(a, idx, mask, r3);
-      store_rows<JR, BF, EXACT, NM, SP, 3 * SP>(a, mask, r3, rb);
+// Overwrite sample p's row of a mode (values j < J) with v (rounded to BF16
+// in BF16 mode).
+template <int JR, bool BF, bool EXACT>
+__device__ __forceinline__ void write_row(float* buf, int ck, int chp, int p, int J, const float (&v)[JR]) {
+#pragma unroll
+  for (int j = 0; j < JR; ++j) {
+    if (EXACT || j < J) {
+      if constexpr (!BF) {
+        buf[((ck + (j >> 2)) * chp + p) * 4 + (j & 3)] = v[j];
+      } else {
+        unsigned short* b16 = reinterpret_cast<unsigned short*>(buf);
+        b16[((ck + (j >> 3)) * chp + p) * 8 + (j & 7)] = bf16_bits(v[j]);
+      }
     }
   }
 }
@@ -368,10 +363,12 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
 
 // hp[h * chp + p] = prod over the remaining modes of the sample's rows at h
 // (1 when there are none); zero for positions p >= cnt.  hmap[khi + h * nhi + i]
-// is the row-buffer offset of remaining mode i at h.  Reads are batched
+// is the position of remaining mode i's value at h in the row buffer less
+// the sample term (p * 4 floats, or p * 8 BF16 values).  Reads are batched
 // ahead of the writes, four h at a time.
-__device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, const float* rowbuf, const int* hmap,
-                                         int cnt, int chp, float* hp) {
+template <bool BF>
+__device__ __forceinline__ void build_hp(const PhaseTab& pt, const float* rowbuf, const int* hmap, int cnt, int chp,
+                                         float* hp) {
   const int p = threadIdx.x;
   if (p >= chp) return;
   const int khi = pt.khi, nhi = pt.nhi;
@@ -383,8 +380,8 @@ __device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, con
     hp[p] = 1.f;
     return;
   }
-  const float* rb = rowbuf + p * s.rs;
   const int* ro = hmap + khi;
+  const unsigned short* b16 = reinterpret_cast<const unsigned short*>(rowbuf);
   for (int h0 = 0; h0 < khi; h0 += 4) {
     float v[4];
 #pragma unroll
@@ -392,7 +389,10 @@ __device__ __forceinline__ void build_hp(const Shape& s, const PhaseTab& pt, con
       const int h = h0 + u;
       v[u] = 1.f;
       if (h < khi)
-        for (int i = 0; i < nhi; ++i) v[u] *= rb[ro[h * nhi + i]];
+        for (int i = 0; i < nhi; ++i) {
+          const int o = ro[h * nhi + i];
+          v[u] *= BF ? bf16_val(b16[o + p * 8]) : rowbuf[o + p * 4];
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -446,24 +446,26 @@ __device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int 
 
 // Where the products hp_p[h] are read from: the hp buffer (hp[h * chp + p]),
 // or, with a single remaining mode (three-mode tensors), that mode's rows in
-// the row buffer directly (hp_p[h] = rowbuf[p * rs + rs_hi + h]).
-template <bool HPV>
+// the row buffer directly.
+template <bool HPV, bool BF>
 struct HpRef {
-  const float* base;
-  int hs, ps;  // strides of h and p
+  const float* base;  // hp buffer, or the row buffer
+  int chp;
+  int ck;             // (row buffer) chunk offset of the remaining mode
+  __device__ __forceinline__ float one(int p, int h) const {
+    if constexpr (!HPV) return base[h * chp + p];
+    else return row_at<BF>(base, ck, chp, p, h);
+  }
   __device__ __forceinline__ f32x4 quad(int p, int h) const {  // samples p .. p+3
     if constexpr (!HPV) {
-      return *reinterpret_cast<const f32x4*>(base + h * hs + p);
+      return *reinterpret_cast<const f32x4*>(base + h * chp + p);
     } else {
       f32x4 v;
-      v[0] = base[p * ps + h];
-      v[1] = base[(p + 1) * ps + h];
-      v[2] = base[(p + 2) * ps + h];
-      v[3] = base[(p + 3) * ps + h];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = row_at<BF>(base, ck, chp, p + i, h);
       return v;
     }
   }
-  __device__ __forceinline__ float one(int p, int h) const { return base[h * hs + p * ps]; }
 };
 
 // E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
@@ -471,13 +473,13 @@ struct HpRef {
 // independent MFMA chains overlap.
 template <int JR, bool BF, bool EXACT, bool HPV, int KHI>
 __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf,
-                                       const HpRef<HPV>& hpr, int cnt, int chp, float* ebuf, int es) {
+                                       const HpRef<HPV, BF>& hpr, int cnt, int chp, float* ebuf, int es) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
   const int Jn = EXACT ? JR : g.Jn;
   const int MT = (cnt + 15) >> 4;
-  const int lo_off = g.rs_lo;
+  const int clo = g.c_lo;
   const int khi = g.khi;
   const int kp = EXACT ? KPX : g.kp;
   const int nt = EXACT ? (JR + 15) / 16 : g.nt;
@@ -498,9 +500,9 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
       for (int ks = 0; ks < KS; ++ks) {
         // no masks: the table rows k >= J_lo are zero, samples p >= cnt are
         // not stored, and the row buffer holds finite values only
-        const int k = 4 * ks + kq;
-        a0[ks] = rowbuf[prow0c * s.rs + lo_off + k];
-        a1[ks] = rowbuf[prow1c * s.rs + lo_off + k];
+        // value k = 4 ks + kq of the lo-mode row: chunk ks, word kq
+        a0[ks] = rowbuf[((clo + ks) * chp + prow0c) * 4 + kq];
+        a1[ks] = rowbuf[((clo + ks) * chp + prow1c) * 4 + kq];
       }
       // One accumulation chain per tile over K = (j_lo, h): the A operand is
       // a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
@@ -531,14 +533,13 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
     } else {
       constexpr int KS = (JR + 15) / 16;
       s16x4 a0[KS], a1[KS];
+      const unsigned short* b16 = reinterpret_cast<const unsigned short*>(rowbuf);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = 16 * ks + 4 * kq + e;
-          a0[ks][e] = (short)bf16_bits(rowbuf[prow0c * s.rs + lo_off + k]);
-          a1[ks][e] = (short)bf16_bits(rowbuf[prow1c * s.rs + lo_off + k]);
-        }
+        // values k = 16 ks + 4 kq + e (e < 4): chunk 2 ks + kq / 2, BF16 words 4 (kq & 1) + e
+        const int ch = clo + 2 * ks + (kq >> 1);
+        a0[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow0c) * 8 + 4 * (kq & 1));
+        a1[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow1c) * 8 + 4 * (kq & 1));
       }
       const int nks = kp >> 4;
       const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * kp + 4 * kq;
@@ -582,7 +583,7 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 // and B column loads and keep three independent MFMA chains in flight.
 template <int JR, bool BF, bool EXACT, bool HPV>
 __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra,
-                                               int ras, const HpRef<HPV>& hpr, int cnt, int chp, float* out) {
+                                               int ras, const HpRef<HPV, BF>& hpr, int cnt, int chp, float* out) {
   constexpr int JG = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -590,7 +591,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
   const int jlo = EXACT ? JR : g.jlo;
   const int khi = g.khi;
   const int MT0 = (J0 + 15) >> 4, NT1 = (jlo + 15) >> 4;
-  const int lo_off = g.rs_lo;
+  const int clo = g.c_lo;
   const int hgroups = (khi + JG - 1) / JG;
   const int jobs = hgroups * MT0 * NT1;
   constexpr int KSTEP = BF ? 16 : 4;
@@ -625,7 +626,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
         for (int u = 0; u < 4; ++u) {
           const int p = (4 * gi + u) * 4 + kq;
           rav[u] = ra[p * ras + j0];
-          bv[u] = rowbuf[p * s.rs + lo_off + jl];
+          bv[u] = rowbuf[((clo + (jl >> 2)) * chp + p) * 4 + (jl & 3)];
 #pragma unroll
           for (int q = 0; q < JG; ++q) hv[u][q] = hpr.one(p, hh[q]);
         }
@@ -657,7 +658,7 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
         for (int e = 0; e < 4; ++e) {  // no masks (see the FP32 path); 16 * nsteps <= chp
           const int p = st * 16 + 4 * kq + e;
           rav[e] = ra[p * ras + j0];
-          bv[e] = (short)bf16_bits(rowbuf[p * s.rs + lo_off + jl]);
+          bv[e] = (short)reinterpret_cast<const unsigned short*>(rowbuf)[((clo + (jl >> 3)) * chp + p) * 8 + (jl & 7)];
         }
 #pragma unroll
         for (int q = 0; q < JG; ++q) {
@@ -729,9 +730,6 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
   constexpr bool BF = BFI != 0;
-  constexpr int CV = RowRegs<JR, BF, 1>::C;
-  // modes whose rows are parked in registers between sub-steps (generic ranks: none)
-  constexpr int NPF = EXACT ? ((12 / CV) < NM ? (12 / CV) : NM) : 0;
   extern __shared__ float lds[];
   const Shape& s = a.s;
   const int N = NU ? NU : s.N;
@@ -746,7 +744,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 
   float* Gs = lds + L.gs;
   float* TB = lds + L.tb;
-  float* rowbuf = lds + L.row;
+  float* const rows0 = lds + L.row0;  // the two row buffers (rows1 = rows0 + rowsz), one per sub-step in turn
+  float* const rows1 = lds + L.row1;
   float* hp = lds + L.hp;
   float* ebuf = lds + L.ebuf;
   float* rabuf = lds + L.ra;
@@ -761,15 +760,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   int* misc = xn + a.W;      // 8
   const int chp = L.chp, es = L.es, ras = L.ras, sstride = L.sstride, wstride = L.wstride;
   const unsigned allm = (1u << N) - 1u;
-  const unsigned npfm = (1u << NPF) - 1u;
   const int XS = xrow_stride(a.W);
   const size_t carry_par_stride = (size_t)a.W * 2 * a.carry_stride;
   const int64_t T = a.T, M = a.M;
 
   // ---- set-up: core, index maps, resident tables
   for (int lin = tid; lin < P; lin += BT) Gs[lin] = a.G[lin];
-  // (plus a zero tail: the MFMA K steps read up to 31 words past a row)
-  for (int i = tid; i < chp * s.rs + kRowTail; i += BT) rowbuf[i] = 0.f;
+  // (both row buffers and a zero tail: the MFMA K steps read up to 31 words past a row)
+  for (int i = tid; i < 2 * L.rowsz + kRowTail; i += BT) rows0[i] = 0.f;
   for (int i = tid; i < L.aux_len; i += BT) {
     const int v = a.aux[i];
     if (i < L.hm_len) hmap[i] = v;
@@ -791,7 +789,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   LaneRec<NM> cur;
   if (a.b_begin < a.b_end) load_lane_rec<NM>(a, N, a.b_begin, 0, cur);
   else cur.valid = false;
-  RowRegs<JR, BF, NPF> pf;   // next phase's rows, loaded during this phase
+  int bsel = 0;  // which row buffer holds the current sub-step's rows
   float an_cur[JR], an_nxt[JR];  // BF16 mode: FP32 master row of the lane's own-mode row
 #pragma unroll
   for (int j = 0; j < JR; ++j) an_cur[j] = an_nxt[j] = 0.f;
@@ -809,7 +807,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       const int pm = first ? -1 : pt.pm;
       const bool active = tid < cnt;
       const bool splits = pm >= 0 && a.W > 1;
-      float* rb = rowbuf + tid * s.rs;
+      float* const rowbuf = bsel ? rows1 : rows0;
+      float* const rownext = bsel ? rows0 : rows1;
 
       // ---- 1. after the barrier, one batch of loads: the rows of the modes
       //      the two previous phases updated, the carry slots and boundary
@@ -818,7 +817,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       const f32x4* psrc = reinterpret_cast<const f32x4*>(a.partial);
       f32x4 pp[8];  // core phase 1: the first 8 workgroups' partials of column tid
       {
-        const unsigned post = first ? allm : (((unsigned)pt.post | (allm & ~npfm)) & allm);
+        const unsigned post = first ? allm : ((unsigned)pt.post & allm);
         const int64_t bp = ph == 0 ? b - 1 : b;
         const int* xsrc = a.xrow + ((size_t)(splits ? bp : 0) * N + (splits ? pm : 0)) * XS;
         const int ctot = (int)(carry_par_stride >> 2);
@@ -840,7 +839,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           for (int v = 0; v < 8; ++v)
             if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
         }
-        if (active) gather_rows<JR, BF, EXACT, NM>(a, cur.idx, post, rb);
+        issue_rows_lds<JR, BF, EXACT, NM>(a, cur.idx, post, rowbuf, chp, active);
         if (splits) {
           f32x4* cdst = reinterpret_cast<f32x4*>(cbuf);
 #pragma unroll
@@ -854,6 +853,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           if (tid == 0) misc[0] = xc;
         }
       }
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // the rows written straight into LDS have landed
+      __syncthreads();
       // the next phase's record (read-only; its latency overlaps this phase)
       int nph = ph + 1;
       int64_t nbb = b;
@@ -865,7 +866,6 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       LaneRec<NM> nx;
       if (has_next) load_lane_rec<NM>(a, N, nbb, nph, nx);
       else nx.valid = false;
-      __syncthreads();
 
       // ---- 2. core: finish the core step of this minibatch (same in every workgroup)
       if (ph == 1) {
@@ -909,20 +909,19 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         if (active && pe > 0) {
           const int pJ = EXACT ? JR : s.J[pm];
           const float* ent = split + (pe - 1) * sstride + 4;
-          float* dst = rb + s.rs_off[pm];
           float v[JR];
 #pragma unroll
           for (int j = 0; j < JR; ++j) v[j] = (EXACT || j < pJ) ? ent[j] : 0.f;
-#pragma unroll
-          for (int j = 0; j < JR; ++j)
-            if (EXACT || j < pJ) dst[j] = BF ? bf16_round(v[j]) : v[j];
+          write_row<JR, BF, EXACT>(rowbuf, L.coff[pm], chp, tid, pJ, v);
         }
       }
 
-      // ---- 4. the next phase's rows that no phase writes before it: into registers
-      unsigned pre = 0;
-      if (has_next) pre = (allm & ~(unsigned)a.pt[nph].post) & npfm;
-      if (NPF > 0 && nx.valid && pre) issue_rows<JR, BF, EXACT, NM, NPF, 0>(a, nx.idx, pre, pf);
+      // ---- 4. the next phase's rows that no phase writes before it: straight
+      //      into the other row buffer (they land before this phase's arrival)
+      if (has_next) {
+        const unsigned pre = allm & ~(unsigned)a.pt[nph].post;
+        if (pre) issue_rows_lds<JR, BF, EXACT, NM>(a, nx.idx, pre, rownext, chp, nx.valid);
+      }
       if (BF && has_next && nx.valid && nph > 0) {
         const float* src = a.A[a.pt[nph].n] + (int64_t)nx.rown * s.Jp[a.pt[nph].n];
         const int Jx = EXACT ? JR : a.pt[nph].Jn;
@@ -933,12 +932,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 
       // ---- 5. E_p for every sample of the chunk
       constexpr bool HPV = NU == 3;  // one remaining mode: hp is a view of its rows
-      HpRef<HPV> hpr;
+      HpRef<HPV, BF> hpr;
       if constexpr (HPV) {
-        hpr = HpRef<HPV>{rowbuf + pt.rs_hi, 1, s.rs};
+        hpr = HpRef<HPV, BF>{rowbuf, chp, pt.c_hi};
       } else {
-        build_hp(s, pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
-        hpr = HpRef<HPV>{hp, chp, 1};
+        build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
+        hpr = HpRef<HPV, BF>{hp, chp, 0};
       }
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
@@ -949,8 +948,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         // ================= core sub-step =================
         if (tid < chp) {
           float r = 0.f, a0r[JR];
-#pragma unroll
-          for (int j = 0; j < JR; ++j) a0r[j] = (EXACT || j < Jn) ? rb[j] : 0.f;  // mode 0's row sits at offset 0
+          read_row<JR, BF, EXACT>(rowbuf, pt.c_n, chp, min(tid, chp - 1), Jn, a0r);
           if (active) {
             float xh = 0.f;
 #pragma unroll
@@ -970,16 +968,15 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         float u[JR], an[JR];
 #pragma unroll
         for (int j = 0; j < JR; ++j) u[j] = an[j] = 0.f;
-        const int rsn = pt.rs_n;
         if (active) {
-          float xh = 0.f;
+          float xh = 0.f, av[JR];
+          read_row<JR, BF, EXACT>(rowbuf, pt.c_n, chp, tid, Jn, av);
 #pragma unroll
           for (int j = 0; j < JR; ++j) {
             if (EXACT || j < Jn) {
               const float e = ebuf[tid * es + j];
-              const float av = rb[rsn + j];
-              an[j] = BF ? an_cur[j] : av;
-              xh = fmaf(av, e, xh);
+              an[j] = BF ? an_cur[j] : av[j];
+              xh = fmaf(av[j], e, xh);
               u[j] = e;
             }
           }
@@ -1040,11 +1037,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
       }
       // ---- 6. barrier: the next sub-step needs this one's result.  Between
-      //      arrival and wait: park the prefetched rows, build the tables the
-      //      core update changed (neither reads what other workgroups write).
+      //      arrival and wait: build the tables the core update changed (no
+      //      reads of what other workgroups write).
       passed += 1;
       barrier_arrive(a, passed);
-      if (NPF > 0 && nx.valid && pre) store_rows<JR, BF, EXACT, NM, NPF, 0>(a, pre, pf, rb);
       if (ph == 1 && L.tb_all) {
         for (int n2 = 1; n2 < N; ++n2) {
           const PhaseTab& q = a.pt[n2 + 1];
@@ -1053,6 +1049,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       }
       if (!barrier_wait(a, passed, misc + 7)) return;
       first = false;
+      bsel ^= 1;
       cur = nx;
 #pragma unroll
       for (int j = 0; j < JR; ++j) an_cur[j] = an_nxt[j];
@@ -1121,11 +1118,21 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   auto tbf = [&](int len) { return bf ? (size_t)(len + 1) / 2 : (size_t)len; };
   ChainLayout& L = a.lay;
   L.chp = (a.chunk + 15) & ~15;
+  {  // chunk-major row buffers: ceil(J_k / V) 16-byte chunks per mode and sample
+    const int V = bf ? 8 : 4;
+    int c = 0;
+    for (int k = 0; k < kMaxOrder; ++k) {
+      L.coff[k] = c;
+      if (k < N) c += (s.J[k] + V - 1) / V;
+    }
+    L.ctot = c;
+    L.rowsz = L.ctot * L.chp * 4;
+  }
   L.es = 16 * ((jmax + 15) / 16) + 1;
   L.ras = pad4(JR) + 1;
   L.sstride = 4 + pad4(JR);
   L.wstride = pad4(JR) + 4;
-  size_t common = al(s.P) + al((size_t)L.chp * s.rs + kRowTail) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
+  size_t common = al(s.P) + al(2 * (size_t)L.rowsz + kRowTail) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
                   al((size_t)L.chp * L.ras) + al((size_t)a.split_cap * L.sstride) +
                   al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0) + al((size_t)hm_len) +
                   al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
@@ -1134,7 +1141,9 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   size_t off = 0;
   L.gs = (int)off;    off += al(s.P);
   L.tb = (int)off;    off += al(L.tb_all ? tbf(tb_sum) : tbf(tb_max));
-  L.row = (int)off;   off += al((size_t)L.chp * s.rs + kRowTail);
+  L.row0 = (int)off;  // (the two buffers are adjacent: one zero fill covers both and the tail)
+  L.row1 = L.row0 + L.rowsz;
+  off += al(2 * (size_t)L.rowsz + kRowTail);
   L.hp = (int)off;    off += al((size_t)khimax * L.chp);
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras);
@@ -1166,10 +1175,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     t.nt = q.nt;
     t.ls_n = s.lstride[n];
     t.ls_lo = s.lstride[q.lo];
-    t.rs_lo = s.rs_off[q.lo];
-    t.rs_n = s.rs_off[n];
+    t.c_lo = L.coff[q.lo];
+    t.c_n = L.coff[n];
     t.Jn = s.J[n];
-    t.rs_hi = q.nhi > 0 ? s.rs_off[q.hi[0]] : 0;
+    t.c_hi = q.nhi > 0 ? L.coff[q.hi[0]] : 0;
     t.tb_off = L.tb_all ? q.tb_off : 0;
     t.tb_len = q.tb_len;
     t.hm_off = q.hm_off;
@@ -1191,7 +1200,9 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
           const int d = hh % Jk;
           hh /= Jk;
           o += d * s.lstride[q.hi[i]];
-          hm[q.khi + h * q.nhi + i] = s.rs_off[q.hi[i]] + d;
+          // value d of mode hi[i] in the chunk-major row buffer, less the sample term
+          hm[q.khi + h * q.nhi + i] = bf ? (L.coff[q.hi[i]] + d / 8) * L.chp * 8 + d % 8
+                                         : (L.coff[q.hi[i]] + d / 4) * L.chp * 4 + d % 4;
         }
         hm[h] = o;
         hoff[h] = o;
@@ -1248,7 +1259,7 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
   const size_t bytes = (size_t)a.lay.total * 4;
   {  // the plan must be the one these arguments produce
     ChainArgs chk = a;
-    if (plan_chain_lds(chk, threads, a.bf16 != 0) != bytes || chk.lay.cbuf != a.lay.cbuf ||
+    if (plan_chain_lds(chk, threads, a.bf16 != 0) != bytes || chk.lay.cbuf != a.lay.cbuf || chk.lay.row1 != a.lay.row1 ||
         chk.lay.ints != a.lay.ints || chk.lay.tmap != a.lay.tmap || chk.lay.aux_len != a.lay.aux_len ||
         chk.lay.hm_len != a.lay.hm_len || !a.aux)
       return hipErrorInvalidValue;

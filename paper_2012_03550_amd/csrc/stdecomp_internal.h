@@ -31,7 +31,7 @@ struct Shape {
 
 // LDS regions of a chain workgroup (float offsets) and strides.
 struct ChainLayout {
-  int gs, tb, row, hp, ebuf, ra, split, cbuf, hmap, tmap, wscr, ints, total;
+  int gs, tb, row0, row1, hp, ebuf, ra, split, cbuf, hmap, tmap, wscr, ints, total;
   int chp;      // chunk rounded up to 16 (MFMA tile rows)
   int es;       // stride of the E buffer (odd)
   int ras;      // stride of the r * a(0) buffer
@@ -40,6 +40,12 @@ struct ChainLayout {
   int tb_all;   // 1: the tables of every mode stay resident (rebuilt once per minibatch)
   int aux_len;  // ints of the host-built index maps (row-offset maps, then table gather maps)
   int hm_len;   // ints of the row-offset maps (the first part of aux)
+  // Row buffers (two, alternating between sub-steps) are chunk-major: mode
+  // k's values [c*V, c*V + V) (a 16-byte chunk, V = 4 FP32 or 8 BF16 values)
+  // of sample p sit at float word ((coff[k] + c) * chp + p) * 4.
+  int coff[kMaxOrder];
+  int ctot;     // chunks per sample over all modes
+  int rowsz;    // floats of one row buffer
 };
 
 // Per-phase constants of the chain, built on the host.  Phase 0 is the core
@@ -51,8 +57,8 @@ struct PhaseTab {
   int post;      // bit mask of modes whose rows are read after the barrier (updated by the two previous phases)
   int khi, nhi;  // product and count of the modes other than n and lo
   int jlo, kp, nt;
-  int ls_n, ls_lo, rs_lo, rs_n, Jn;
-  int rs_hi;     // row-buffer offset of the first remaining mode (0 if none)
+  int ls_n, ls_lo, Jn;
+  int c_lo, c_n, c_hi;  // chunk offsets (ChainLayout::coff) of modes lo, n and the first remaining mode
   int tb_off;    // element offset of mode n's table in the table region
   int tb_len;    // elements of mode n's table
   int hm_off;    // int offset of mode n's row-offset map
