@@ -114,7 +114,7 @@ def main():
         tj = json.load(open(args.traffic_json))
         if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("dtype") == args.dtype:
             traffic = tj.get("bytes_per_launch")
-    roofline = {"bound": "mfma" if args.dtype == "bf16" else "alu", "achieved": round(achieved, 4), "peak": peak,
+    roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 6), "traffic": traffic,
                 "kernel": "k_chain", "avg_launch_ms": round(avg_launch * 1e3, 3),
                 "hbm_alg_GBs": round(acc["bytes_alg"] / acc["chain_seconds"] / 1e9, 2)}
