@@ -510,26 +510,36 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
       const int nks = kp >> 2;
       const float* tb = TB + (t * kp + kq) * 16 + r16;
       const int hstride = nt * kp * 16;
+      // four independent accumulation chains: (tile 0, tile 1) x (even h, odd h)
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-      auto step = [&](int h) {
+      f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+      auto step = [&](int h, f32x4& x0, f32x4& x1) {
         const float hv0 = hpr.one(prow0c, h), hv1 = hpr.one(prow1c, h);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           if (ks < nks) {
             const float bv = tb[h * hstride + ks * 64];
-            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, c1, 0, 0, 0);
+            x0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv, x0, 0, 0, 0);
+            x1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, x1, 0, 0, 0);
           }
         }
       };
       if constexpr (KHI > 0) {  // trip count known: straight-line code, loads scheduled early
 #pragma unroll
-        for (int h = 0; h < KHI; ++h) step(h);
+        for (int h = 0; h < KHI; h += 2) {
+          step(h, c0, c1);
+          if (h + 1 < KHI) step(h + 1, d0, d1);
+        }
       } else {
-        for (int h = 0; h < khi; ++h) step(h);
+        int h = 0;
+        for (; h + 1 < khi; h += 2) {
+          step(h, c0, c1);
+          step(h + 1, d0, d1);
+        }
+        if (h < khi) step(h, c0, c1);
       }
-      e0 = c0;
-      e1 = c1;
+      e0 = c0 + d0;
+      e1 = c1 + d1;
     } else {
       constexpr int KS = (JR + 15) / 16;
       s16x4 a0[KS], a1[KS];
@@ -576,110 +586,91 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
   }
 }
 
-// partial[lin] = sum over the chunk of r_p h_p[lin], lin = j0 + J0 (j_lo + J_lo h)
-// (MFMA over samples; ra[p * ras + j0] = r_p a(0)_p[j0], hp rows zero for
-// p >= cnt).  Jobs are (h, j0 tile, j_lo tile); a wave carries up to three
-// jobs with the same tiles and consecutive h at once, which share the A row
-// and B column loads and keep three independent MFMA chains in flight.
+// partial[lin] = sum over the chunk of r_p h_p[lin], lin = j0 + J0 * col with
+// col = j_lo + J_lo h: the GEMM dG[j0, col] = sum_p ra[p][j0] * B[p][col],
+// B[p][col] = a(lo)_p[j_lo] hp_p[h] (ra[p * ras + j0] = r_p a(0)_p[j0], zero
+// for p >= cnt), K = the chunk's samples.  The columns are packed, so J_lo khi
+// of them fill ceil(J_lo khi / 16) tiles; a wave runs two output tiles at a
+// time (two independent MFMA chains sharing the A loads when they share rows).
 template <int JR, bool BF, bool EXACT, bool HPV>
 __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g, const float* rowbuf, const float* ra,
                                                int ras, const HpRef<HPV, BF>& hpr, int cnt, int chp, float* out) {
-  constexpr int JG = 3;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int J0 = EXACT ? JR : g.Jn;  // the core phase contracts with mode 0
   const int jlo = EXACT ? JR : g.jlo;
   const int khi = g.khi;
-  const int MT0 = (J0 + 15) >> 4, NT1 = (jlo + 15) >> 4;
+  const int ncol = jlo * khi;
+  const int MT0 = EXACT && JR <= 16 ? 1 : (J0 + 15) >> 4;
+  const int NTC = (ncol + 15) >> 4;
   const int clo = g.c_lo;
-  const int hgroups = (khi + JG - 1) / JG;
-  const int jobs = hgroups * MT0 * NT1;
+  const int jobs = MT0 * NTC;
   constexpr int KSTEP = BF ? 16 : 4;
-  const int nsteps = (cnt + KSTEP - 1) / KSTEP;
-  for (int job = wv; job < jobs; job += nwaves) {
-    const int hg = job / (MT0 * NT1);
-    const int rem = job - hg * MT0 * NT1;
-    const int t0 = rem / NT1, t1 = rem - t0 * NT1;
-    const int j0 = 16 * t0 + r16;  // A row
-    const int jl = 16 * t1 + r16;  // B column
-    const bool bcol = jl < jlo;
-    const int h0 = hg * JG;
-    int hh[JG];
-    bool hok[JG];
-#pragma unroll
-    for (int q = 0; q < JG; ++q) {
-      hok[q] = h0 + q < khi;
-      hh[q] = hok[q] ? h0 + q : h0;
-    }
-    f32x4 c[JG];
-#pragma unroll
-    for (int q = 0; q < JG; ++q) c[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nsteps = (cnt + KSTEP - 1) / KSTEP;  // KSTEP * nsteps <= chp
+  for (int jb = wv; jb < jobs; jb += 2 * nwaves) {
+    const int jb2 = min(jb + nwaves, jobs - 1);  // second tile (a repeat of the first when absent: not stored)
+    const bool has2 = jb + nwaves < jobs;
+    const int t0a = MT0 == 1 ? 0 : jb / NTC, tca = jb - t0a * NTC;
+    const int t0b = MT0 == 1 ? 0 : jb2 / NTC, tcb = jb2 - t0b * NTC;
+    const int j0a = 16 * t0a + r16, j0b = 16 * t0b + r16;  // A rows of this lane
+    const int cola = 16 * tca + r16, colb = 16 * tcb + r16;  // B columns of this lane
+    const int ca = min(cola, ncol - 1), cb = min(colb, ncol - 1);
+    const int ha = ca / jlo, jla = ca - ha * jlo, hb = cb / jlo, jlb = cb - hb * jlo;
+    f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF) {
-      // K in groups of four steps (16 samples; 16 * groups <= chp), the
-      // operands of group g+1 read before the MFMAs of group g.  No masks:
-      // positions p >= cnt have zero r a(0) (and zero hp), the row buffer
-      // holds finite values only; rows j0 >= J0 and columns jl >= J_lo
-      // reach only outputs that are not stored.
+      // K in groups of four steps (16 samples), the operands of group gi+1
+      // read before the MFMAs of group gi.  No masks: positions p >= cnt have
+      // zero r a(0), the row buffer holds finite values only, and rows j0 >= J0
+      // and columns col >= J_lo khi reach only outputs that are not stored.
       const int ngroups = (nsteps + 3) >> 2;
-      auto load = [&](int gi, float (&rav)[4], float (&bv)[4], float (&hv)[4][JG]) {
+      auto load = [&](int gi, float (&aa)[4], float (&ab)[4], float (&ba)[4], float (&bb)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int p = (4 * gi + u) * 4 + kq;
-          rav[u] = ra[p * ras + j0];
-          bv[u] = rowbuf[((clo + (jl >> 2)) * chp + p) * 4 + (jl & 3)];
-#pragma unroll
-          for (int q = 0; q < JG; ++q) hv[u][q] = hpr.one(p, hh[q]);
+          aa[u] = ra[p * ras + j0a];
+          ab[u] = ra[p * ras + j0b];
+          ba[u] = rowbuf[((clo + (jla >> 2)) * chp + p) * 4 + (jla & 3)] * hpr.one(p, ha);
+          bb[u] = rowbuf[((clo + (jlb >> 2)) * chp + p) * 4 + (jlb & 3)] * hpr.one(p, hb);
         }
       };
-      float rav[4], bv[4], hv[4][JG];
-      if (ngroups > 0) load(0, rav, bv, hv);
+      float aa[4], ab[4], ba[4], bb[4];
+      if (ngroups > 0) load(0, aa, ab, ba, bb);
       for (int gi = 0; gi < ngroups; ++gi) {
-        float rn[4], bn[4], hn[4][JG];
-        load(gi + 1 < ngroups ? gi + 1 : gi, rn, bn, hn);
+        float na[4], nb[4], nc[4], nd[4];
+        load(gi + 1 < ngroups ? gi + 1 : gi, na, nb, nc, nd);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-#pragma unroll
-          for (int q = 0; q < JG; ++q)
-            c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rav[u] * hv[u][q], bv[u], c[q], 0, 0, 0);
+          acca = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[u], ba[u], acca, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[u], bb[u], accb, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          rav[u] = rn[u];
-          bv[u] = bn[u];
-#pragma unroll
-          for (int q = 0; q < JG; ++q) hv[u][q] = hn[u][q];
+          aa[u] = na[u];
+          ab[u] = nb[u];
+          ba[u] = nc[u];
+          bb[u] = nd[u];
         }
       }
     } else {
-      for (int st = 0; st < nsteps; ++st) {
-        float rav[4];
-        s16x4 bv;
+      for (int st = 0; st < nsteps; ++st) {  // no masks (see the FP32 path); 16 * nsteps <= chp
+        s16x4 aa, ab, ba, bb;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {  // no masks (see the FP32 path); 16 * nsteps <= chp
+        for (int e = 0; e < 4; ++e) {
           const int p = st * 16 + 4 * kq + e;
-          rav[e] = ra[p * ras + j0];
-          bv[e] = (short)reinterpret_cast<const unsigned short*>(rowbuf)[((clo + (jl >> 3)) * chp + p) * 8 + (jl & 7)];
+          aa[e] = (short)bf16_bits(ra[p * ras + j0a]);
+          ab[e] = (short)bf16_bits(ra[p * ras + j0b]);
+          ba[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jla) * hpr.one(p, ha));
+          bb[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jlb) * hpr.one(p, hb));
         }
-#pragma unroll
-        for (int q = 0; q < JG; ++q) {
-          s16x4 av;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int p = st * 16 + 4 * kq + e;
-            av[e] = (short)bf16_bits(rav[e] * hpr.one(p, hh[q]));
-          }
-          c[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c[q], 0, 0, 0);
-        }
+        acca = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa, ba, acca, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab, bb, accb, 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int q = 0; q < JG; ++q) {
-      if (!hok[q]) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int jr = 16 * t0 + 4 * kq + i;
-        if (jr < J0 && bcol) out[jr + J0 * (jl + jlo * (h0 + q))] = c[q][i];
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int jra = 16 * t0a + 4 * kq + i, jrb = 16 * t0b + 4 * kq + i;
+      if (jra < J0 && cola < ncol) out[jra + J0 * cola] = acca[i];
+      if (has2 && jrb < J0 && colb < ncol) out[jrb + J0 * colb] = accb[i];
     }
   }
 }
