@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=60,
                     help="minibatches of the CPU oracle baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "chain_traffic.json"))
+    ap.add_argument("--config", default="c2", choices=["c2", "c3"],
+                    help="c2: Netflix-shaped ratings (default); c3: 4-order planted power-law tensor, FP32 vs BF16")
+    ap.add_argument("--epochs", type=int, default=5, help="(c3) epochs per precision")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -57,6 +60,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c3":
+        run_c3(args)
+        return
 
     import numpy as np
     import torch
@@ -148,6 +154,92 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def run_c3(args):
+    """4-order planted power-law tensor 100000x100000x1000x100, 200M entries
+    (Zipf 1.2 on modes 1-2, uniform on 3-4), planted rank (8,8,8,8) plus
+    N(0, 0.05^2) noise, 10% held out; J = (8,8,8,8), M = 8192, lr = 0.05,
+    lambda = 1e-4 (at lr = lambda = 0.01, or lambda = 1e-3, the model decays
+    to the zero saddle and stays there; at lr = 0.1 it diverges in the first
+    epoch), ``--epochs`` epochs in FP32 and in BF16 from the same initial
+    parameters.  Precision: the FP64 oracle, the FP32 chain and the BF16 chain
+    run the same first 100 minibatches of epoch 0 and their held-out RMSE is
+    compared on a 200,000-entry sample of the held-out set."""
+    import numpy as np
+    import torch
+    from oracle import oracle
+    from paper_2012_03550_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    nnz = args.nnz if args.nnz != 100_000_000 else 200_000_000
+    t = time.time()
+    wl = synth.planted_powerlaw(nnz=nnz, device="cuda")
+    log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
+    M, lr, lam, prefix, sample = 8192, 0.05, 1e-4, 100, 200_000
+    test_idx = torch.from_numpy(wl.test_idx).cuda()
+    test_vals = torch.from_numpy(wl.test_vals).cuda()
+    s_idx = np.ascontiguousarray(wl.test_idx[:, :sample])
+    s_vals = np.ascontiguousarray(wl.test_vals[:sample])
+    res = {}
+    A0 = G0 = None
+    for dtype in ("f32", "bf16"):
+        h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
+                             lam_factor=lam, lam_core=lam, seed_sample=3003, seed_init=2003, dtype=dtype)
+        if A0 is None:
+            A0, G0 = h.get_params()
+        h.run_minibatches(0, 0, prefix)
+        prefix_rmse = h.loss(s_idx, s_vals)["rmse"]
+        h.set_params(A0, G0)
+        h.set_epoch(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev = 0.0
+        rmse = []
+        done = 0
+        for e in range(args.epochs):
+            try:
+                st = h.epoch(1)
+            except binding.StdecompError as ex:
+                log("c3 %s epoch %d: %s" % (dtype, e, ex))
+                rmse.append("diverged")
+                break
+            done += 1
+            dev += st["device_seconds"]
+            rmse.append(round(h.loss(test_idx, test_vals)["rmse"], 6))
+            log("c3 %s epoch %d: chain %.3fs held-out RMSE %.5f" % (dtype, e, st["chain_seconds"], rmse[-1]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        info = h.info()
+        h.close()
+        res[dtype] = {"updates_per_s": round(wl.nnz * done / wall, 1) if done else None, "device_updates_per_s":
+                      round(wl.nnz * done / dev, 1) if done else None, "heldout_rmse_per_epoch": rmse,
+                      "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
+                      "chain_chunk": info["chunk"]}
+    oracle.build()
+    ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    log("oracle: running %d minibatches of epoch 0" % prefix)
+    t = time.perf_counter()
+    ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3003, epoch0=0, n_epochs=1, max_batches=prefix)
+    dt = time.perf_counter() - t
+    orc = ref.loss(s_idx, s_vals)["rmse"]
+    log("oracle: %d minibatches in %.1fs, sample held-out RMSE %.6f" % (prefix, dt, orc))
+    precision = {"prefix_minibatches": prefix, "heldout_sample": sample, "rmse_oracle_f64": orc,
+                 "rmse_f32": res["f32"]["prefix_heldout_rmse_sample"], "rmse_bf16": res["bf16"]["prefix_heldout_rmse_sample"],
+                 "f32_rel_gap": (res["f32"]["prefix_heldout_rmse_sample"] - orc) / orc,
+                 "bf16_rel_gap": (res["bf16"]["prefix_heldout_rmse_sample"] - orc) / orc}
+    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": res["f32"]["updates_per_s"],
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.epochs, "warmup": 0, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "planted_powerlaw 100000x100000x1000x100, %d entries (Zipf 1.2 on modes 1-2, "
+                                  "uniform on 3-4), planted rank 8^4 + N(0,0.05^2), 10%% held out; J=(8,8,8,8), "
+                                  "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
+                      "train_entries": int(wl.nnz), "batch": M},
+           "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
+           "cpu_baseline": {"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1,
+                            "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix}}
+    print(json.dumps(out), flush=True)
+
+
 def kernel_source_hash():
     import hashlib
     hsh = hashlib.sha256()
@@ -165,6 +257,7 @@ def cpu_baseline(h, wl, A0, G0, M, lr, lam, nbatches):
     from paper_2012_03550_amd import binding
     oracle.build()
     ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    log("oracle: running %d minibatches of epoch 0" % prefix)
     t = time.perf_counter()
     ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3002, epoch0=0, n_epochs=1,
             max_batches=nbatches)

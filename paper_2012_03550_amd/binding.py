@@ -103,6 +103,18 @@ def _is_device(x):
     return hasattr(x, "is_cuda") and x.is_cuda
 
 
+def _dev_coo(idx, vals=None):
+    """Device COO in the library's layout: int32 [N][nnz] indices, float32 values."""
+    import torch
+    idx = idx.to(torch.int32).contiguous()
+    if vals is not None:
+        assert _is_device(vals) and vals.device == idx.device, "indices and values must be on the same device"
+        vals = vals.to(torch.float32).contiguous()
+    # the library reads them on its own stream
+    torch.cuda.current_stream(idx.device).synchronize()
+    return idx if vals is None else (idx, vals)
+
+
 def _ptr(x):
     if _is_device(x):
         return ctypes.c_void_p(x.data_ptr())
@@ -120,8 +132,7 @@ class Stdecomp:
         self.ranks = tuple(int(r) for r in ranks)
         on_dev = _is_device(idx)
         if on_dev:
-            assert _is_device(vals)
-            idx_c, vals_c = idx.contiguous(), vals.contiguous()
+            idx_c, vals_c = _dev_coo(idx, vals)
             nnz = idx_c.shape[1]
         else:
             idx_c = np.ascontiguousarray(idx, np.int32)
@@ -185,7 +196,7 @@ class Stdecomp:
     def predict(self, idx):
         if _is_device(idx):
             import torch
-            idx = idx.contiguous()
+            idx = _dev_coo(idx)
             out = torch.empty(idx.shape[1], dtype=torch.float32, device=idx.device)
             self._check(load().stdecomp_predict(self._h, idx.shape[1], _ptr(idx), _ptr(out), 1), "stdecomp_predict")
             return out
@@ -199,7 +210,7 @@ class Stdecomp:
         if idx is None:
             rc = load().stdecomp_loss(self._h, 0, None, None, 0, ctypes.byref(out))
         elif _is_device(idx):
-            idx, vals = idx.contiguous(), vals.contiguous()
+            idx, vals = _dev_coo(idx, vals)
             rc = load().stdecomp_loss(self._h, idx.shape[1], _ptr(idx), _ptr(vals), 1, ctypes.byref(out))
         else:
             idx = np.ascontiguousarray(idx, np.int32)

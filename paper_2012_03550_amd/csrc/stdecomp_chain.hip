@@ -469,11 +469,13 @@ struct HpRef {
 };
 
 // E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
-// header).  Each wave carries two 16-sample tiles at once so that two
-// independent MFMA chains overlap.
-template <int JR, bool BF, bool EXACT, bool HPV, int KHI>
+// header).  A job is TPJ 16-sample tiles (one, or two sharing the B loads)
+// times one 16-wide j_n tile; the caller picks TPJ = 1 when there are at
+// least as many waves as single-tile jobs.
+template <int JR, bool BF, bool EXACT, bool HPV, int KHI, int TPJ>
 __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf,
                                        const HpRef<HPV, BF>& hpr, int cnt, int chp, float* ebuf, int es) {
+  constexpr bool TWO = TPJ == 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
@@ -483,44 +485,41 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
   const int khi = g.khi;
   const int kp = EXACT ? KPX : g.kp;
   const int nt = EXACT ? (JR + 15) / 16 : g.nt;
-  const int jlo = EXACT ? JR : g.jlo;
-  const int jobs = ((MT + 1) >> 1) * nt;  // job = (tile pair, j_n tile)
+  const int jobs = ((MT + TPJ - 1) / TPJ) * nt;  // job = (tile group, j_n tile)
   for (int job = wv; job < jobs; job += nwaves) {
     const int mp = job / nt, t = job - mp * nt;
-    const int mt0 = 2 * mp, mt1 = 2 * mp + 1;
+    const int mt0 = TPJ * mp, mt1 = mt0 + 1;
     const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
     const int prow0c = min(prow0, chp - 1), prow1c = min(prow1, chp - 1);
     f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
-    const int hq0 = mt0 * 16 + 4 * kq;
-    const int hq1 = min(mt1, MT - 1) * 16 + 4 * kq;  // (a missing tile mt1 is never stored)
     if constexpr (!BF) {
       constexpr int KS = (JR + 3) / 4;
       float a0[KS], a1[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         // no masks: the table rows k >= J_lo are zero, samples p >= cnt are
-        // not stored, and the row buffer holds finite values only
+        // not stored, and the row buffer holds finite values only.
         // value k = 4 ks + kq of the lo-mode row: chunk ks, word kq
         a0[ks] = rowbuf[((clo + ks) * chp + prow0c) * 4 + kq];
-        a1[ks] = rowbuf[((clo + ks) * chp + prow1c) * 4 + kq];
+        a1[ks] = TWO ? rowbuf[((clo + ks) * chp + prow1c) * 4 + kq] : 0.f;
       }
-      // One accumulation chain per tile over K = (j_lo, h): the A operand is
-      // a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
-      // stage folds into the MFMA chain.
+      // One accumulation chain per tile and parity of h over K = (j_lo, h):
+      // the A operand is a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row),
+      // so the second stage folds into the MFMA chain.
       const int nks = kp >> 2;
       const float* tb = TB + (t * kp + kq) * 16 + r16;
       const int hstride = nt * kp * 16;
-      // four independent accumulation chains: (tile 0, tile 1) x (even h, odd h)
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
       auto step = [&](int h, f32x4& x0, f32x4& x1) {
-        const float hv0 = hpr.one(prow0c, h), hv1 = hpr.one(prow1c, h);
+        const float hv0 = hpr.one(prow0c, h);
+        const float hv1 = TWO ? hpr.one(prow1c, h) : 0.f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           if (ks < nks) {
             const float bv = tb[h * hstride + ks * 64];
             x0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv, x0, 0, 0, 0);
-            x1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, x1, 0, 0, 0);
+            if constexpr (TWO) x1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, x1, 0, 0, 0);
           }
         }
       };
@@ -549,11 +548,13 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
         // values k = 16 ks + 4 kq + e (e < 4): chunk 2 ks + kq / 2, BF16 words 4 (kq & 1) + e
         const int ch = clo + 2 * ks + (kq >> 1);
         a0[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow0c) * 8 + 4 * (kq & 1));
-        a1[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow1c) * 8 + 4 * (kq & 1));
+        if constexpr (TWO) a1[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow1c) * 8 + 4 * (kq & 1));
       }
       const int nks = kp >> 4;
       const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * kp + 4 * kq;
       const int hstride = nt * 16 * kp;
+      const int hq0 = mt0 * 16 + 4 * kq;
+      const int hq1 = min(mt1, MT - 1) * 16 + 4 * kq;  // (a missing tile mt1 is never stored)
       for (int h = 0; h < khi; ++h) {
         f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -561,19 +562,17 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
           if (ks < nks) {
             const s16x4 bv = *reinterpret_cast<const s16x4*>(tb + h * hstride + 16 * ks);
             c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[ks], bv, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
+            if constexpr (TWO) c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
           }
         }
         const f32x4 h0 = hpr.quad(hq0, h);
-        const f32x4 h1 = hpr.quad(hq1, h);
-        e0[0] = fmaf(c0[0], h0[0], e0[0]);
-        e0[1] = fmaf(c0[1], h0[1], e0[1]);
-        e0[2] = fmaf(c0[2], h0[2], e0[2]);
-        e0[3] = fmaf(c0[3], h0[3], e0[3]);
-        e1[0] = fmaf(c1[0], h1[0], e1[0]);
-        e1[1] = fmaf(c1[1], h1[1], e1[1]);
-        e1[2] = fmaf(c1[2], h1[2], e1[2]);
-        e1[3] = fmaf(c1[3], h1[3], e1[3]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e0[i] = fmaf(c0[i], h0[i], e0[i]);
+        if constexpr (TWO) {
+          const f32x4 h1 = hpr.quad(hq1, h);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) e1[i] = fmaf(c1[i], h1[i], e1[i]);
+        }
       }
     }
     const int jn = 16 * t + r16;
@@ -581,7 +580,7 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
     for (int i = 0; i < 4; ++i) {
       const int p0 = mt0 * 16 + 4 * kq + i, p1 = mt1 * 16 + 4 * kq + i;
       if (p0 < cnt && jn < Jn) ebuf[p0 * es + jn] = e0[i];
-      if (p1 < cnt && jn < Jn) ebuf[p1 * es + jn] = e1[i];
+      if (TWO && p1 < cnt && jn < Jn) ebuf[p1 * es + jn] = e1[i];
     }
   }
 }
@@ -932,7 +931,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       }
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
-      mfma_E<JR, BF, EXACT, HPV, (EXACT && NU == 3) ? JR : 0>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+      constexpr int KHI = (EXACT && NU == 3) ? JR : 0;  // h trip count of three-mode equal-rank kernels
+      if (((cnt + 15) >> 4) * pt.nt <= (BT >> 6))  // enough waves for one tile each
+        mfma_E<JR, BF, EXACT, HPV, KHI, 1>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+      else
+        mfma_E<JR, BF, EXACT, HPV, KHI, 2>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
       __syncthreads();
 
       if (ph == 0) {

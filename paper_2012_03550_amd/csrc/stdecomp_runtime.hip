@@ -119,13 +119,20 @@ struct HostRng {
 
 int64_t total_minibatches(int64_t T, int64_t M) { return (T + M - 1) / M; }
 
-// Four waves per chain workgroup whatever the chunk: the MFMA tiles and
-// table builds use all of them, the per-sample steps the first `chunk` lanes.
+// Four waves per chain workgroup (one per SIMD) whatever the chunk: the MFMA
+// tiles and table builds use all of them, the per-sample steps the first
+// `chunk` lanes.  (Eight waves hide more latency in the contraction but cost
+// more at every workgroup barrier; measured slower overall.)
 int chain_threads_for(int /*chunk*/) { return stdk::kChainThreads; }
 
 // Pick the chain geometry and check that it fits one workgroup's LDS.
 int configure_chain(stdecomp_handle* h, int chunk_req) {
   const stdk::Shape& s = h->s;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
+    return fail(h, STD_E_DEVICE, "hipGetDeviceProperties failed");
+  const size_t lds_cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                                : prop.sharedMemPerBlock;
   int chunk = chunk_req;
   if (chunk <= 0) {
     // about 32 workgroups for large minibatches, at least 64 entries each
@@ -135,36 +142,41 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
   }
   if (chunk > stdk::kChainThreads) chunk = stdk::kChainThreads;
   if (chunk > h->M) chunk = (int)h->M;
-  int W = (int)((h->M + chunk - 1) / chunk);
-  if (W > h->num_cus) return fail(h, STD_E_INVAL, "minibatch needs more chain workgroups than compute units");
-  h->chunk = chunk;
-  h->W = W;
-  h->threads = chain_threads_for(chunk);
-  h->split_cap = W > 1 ? W - 1 : 0;
-  int jmax = 0;
-  for (int n = 0; n < s.N; ++n) jmax = s.J[n] > jmax ? s.J[n] : jmax;
-  h->carry_stride = stdk::pad4(2 + 2 * jmax);
-  stdk::ChainArgs a{};
-  a.s = s;
-  a.W = W;
-  a.chunk = chunk;
-  a.split_cap = h->split_cap;
-  a.carry_stride = h->carry_stride;
-  h->chain_lds = stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16);
-  if (h->chain_lds == 0) return fail(h, STD_E_INVAL, "inconsistent chain plan");
-  h->aux_host.assign((size_t)(a.lay.aux_len > 0 ? a.lay.aux_len : 1), 0);
-  if (stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16, h->aux_host.data()) != h->chain_lds)
-    return fail(h, STD_E_INVAL, "inconsistent chain plan");
-  h->lay = a.lay;
-  for (int i = 0; i <= kMaxOrder; ++i) h->pt[i] = a.pt[i];
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess)
-    return fail(h, STD_E_DEVICE, "hipGetDeviceProperties failed");
-  const size_t lds_cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
-                                                                : prop.sharedMemPerBlock;
-  if (h->chain_lds > lds_cap)
-    return fail(h, STD_E_INVAL, "core or factor rows too large for one workgroup's LDS (" +
-                                    std::to_string(h->chain_lds) + " > " + std::to_string(lds_cap) + " bytes)");
+  for (;;) {
+    int W = (int)((h->M + chunk - 1) / chunk);
+    if (W > h->num_cus) return fail(h, STD_E_INVAL, "minibatch needs more chain workgroups than compute units");
+    h->chunk = chunk;
+    h->W = W;
+    h->threads = chain_threads_for(chunk);
+    h->split_cap = W > 1 ? W - 1 : 0;
+    int jmax = 0;
+    for (int n = 0; n < s.N; ++n) jmax = s.J[n] > jmax ? s.J[n] : jmax;
+    h->carry_stride = stdk::pad4(2 + 2 * jmax);
+    stdk::ChainArgs a{};
+    a.s = s;
+    a.W = W;
+    a.chunk = chunk;
+    a.split_cap = h->split_cap;
+    a.carry_stride = h->carry_stride;
+    h->chain_lds = stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16);
+    if (h->chain_lds == 0) return fail(h, STD_E_INVAL, "inconsistent chain plan");
+    // With the default chunk, halve it (more, smaller workgroups) until the
+    // row buffers of one workgroup fit its LDS.
+    if (h->chain_lds > lds_cap && chunk_req <= 0 && chunk > 64 &&
+        (h->M + chunk / 2 - 1) / (chunk / 2) <= h->num_cus) {
+      chunk /= 2;
+      continue;
+    }
+    if (h->chain_lds > lds_cap)
+      return fail(h, STD_E_INVAL, "core or factor rows too large for one workgroup's LDS (" +
+                                      std::to_string(h->chain_lds) + " > " + std::to_string(lds_cap) + " bytes)");
+    h->aux_host.assign((size_t)(a.lay.aux_len > 0 ? a.lay.aux_len : 1), 0);
+    if (stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16, h->aux_host.data()) != h->chain_lds)
+      return fail(h, STD_E_INVAL, "inconsistent chain plan");
+    h->lay = a.lay;
+    for (int i = 0; i <= kMaxOrder; ++i) h->pt[i] = a.pt[i];
+    break;
+  }
   return STD_OK;
 }
 

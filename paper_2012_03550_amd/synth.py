@@ -76,6 +76,29 @@ def evaluate_planted(A, G, ranks, idx, chunk=1 << 18):
     return out
 
 
+def evaluate_planted_device(A, G, ranks, idx, device, chunk=1 << 20):
+    """The same values as ``evaluate_planted`` (float64) computed with torch on
+    ``device`` (for workloads of hundreds of millions of entries): the core is
+    contracted with mode 0's rows by a matrix product, then with the other
+    modes' rows one at a time."""
+    import torch
+    N = len(A)
+    T = idx.shape[1]
+    At = [torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(device) for a in A]
+    # flat core index j_0 + J_0 (j_1 + J_1 (...)): rows of this view are (j_{N-1}, ..., j_1) in C order
+    core = torch.from_numpy(np.asarray(G, np.float64)).to(device).view(-1, ranks[0]).t().contiguous()
+    out = np.empty(T, np.float64)
+    for lo in range(0, T, chunk):
+        hi = min(T, lo + chunk)
+        ii = torch.from_numpy(np.ascontiguousarray(idx[:, lo:hi], np.int64)).to(device)
+        x = At[0][ii[0]] @ core  # (z, prod_{k>=1} J_k), j_1 fastest
+        for k in range(1, N):
+            rk = At[k][ii[k]]  # (z, J_k)
+            x = torch.bmm(x.view(hi - lo, -1, ranks[k]), rk.unsqueeze(2).contiguous()).view(hi - lo, -1)
+        out[lo:hi] = x.view(-1).cpu().numpy()
+    return out
+
+
 def split_holdout(rng, T, frac):
     """Boolean mask of held-out entries (each entry independently with prob. frac)."""
     return rng.random(T) < frac
@@ -140,9 +163,10 @@ def ratings_zipf(dims=(480_000, 18_000, 2_000), ranks=(10, 10, 10), nnz=100_000_
 
 
 def planted_powerlaw(dims=(100_000, 100_000, 1_000, 100), ranks=(8, 8, 8, 8), nnz=200_000_000,
-                     s=1.2, powerlaw_modes=2, sigma=0.05, holdout=0.1, seed=1003):
+                     s=1.2, powerlaw_modes=2, sigma=0.05, holdout=0.1, seed=1003, device=None):
     """Power-law (Zipf s) indices on the first ``powerlaw_modes`` modes, uniform
-    on the rest; planted model with N(0,1)/sqrt(J) entries plus N(0, sigma^2)."""
+    on the rest; planted model with N(0,1)/sqrt(J) entries plus N(0, sigma^2).
+    With ``device`` the planted values are computed there (torch, float64)."""
     rng = _rng(seed)
     rows = []
     for k, I in enumerate(dims):
@@ -150,7 +174,8 @@ def planted_powerlaw(dims=(100_000, 100_000, 1_000, 100), ranks=(8, 8, 8, 8), nn
     idx = np.stack(rows)
     A, G = planted_model(rng, dims, ranks)
     noise = rng.standard_normal(nnz) * sigma
-    vals = (evaluate_planted(A, G, ranks, idx) + noise).astype(np.float32)
+    clean = evaluate_planted(A, G, ranks, idx) if device is None else evaluate_planted_device(A, G, ranks, idx, device)
+    vals = (clean + noise).astype(np.float32)
     mask = split_holdout(rng, nnz, holdout)
     return Workload(dims, ranks, idx, vals, mask, planted=(A, G), noise=noise[~mask],
                     name="planted_powerlaw")
