@@ -84,6 +84,9 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libstdecomp.so is not built: run `python -m paper_2012_03550_amd.build`")
+        # torch first, so that the library binds to the HIP runtime torch has
+        # loaded: two runtimes in one process do not share the device
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -319,43 +319,82 @@ __device__ __forceinline__ void build_table_map(const float* Gs, const int* tmap
 }
 
 // The same table without a map (when the maps do not fit in LDS): index
-// arithmetic per element; hmap[h] is the core offset of multi-index h.
-template <bool BF>
-__device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const float* Gs, const int* hmap, float* TB) {
-  const int total = pt.tb_len;
+// arithmetic per element; hmap[h] is the core offset of multi-index h.  With
+// compile-time equal ranks every mode's table has its zero entries (k >= J_lo,
+// j_n >= J_n) in the same places, so they are written once at set-up
+// (zero_only) and each rebuild writes only the J_lo J_n khi core values.
+template <int JR, bool BF, bool EXACT>
+__device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const float* Gs, const int* hmap, float* TB,
+                                                  bool zero_only = false) {
   unsigned short* TB16 = reinterpret_cast<unsigned short*>(TB);
   const int BT = blockDim.x;
-  for (int e0 = threadIdx.x; e0 < total; e0 += 4 * BT) {
-    float v[4];
+  if constexpr (EXACT) {
+    constexpr int KP = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
+    constexpr int NT = (JR + 15) / 16;
+    if (zero_only) {
+      const int total = pt.tb_len;
+      for (int e = threadIdx.x; e < total; e += BT) {
+        if (BF) TB16[e] = 0;
+        else TB[e] = 0.f;
+      }
+      return;
+    }
+    constexpr int PER_H = JR * JR;  // (k, j_n) pairs of one h
+    const int total = pt.khi * PER_H;
+    for (int q0 = threadIdx.x; q0 < total; q0 += 4 * BT) {
+      float v[4];
+      int e[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * BT;
-      v[u] = 0.f;
-      if (e < total) {
-        int k, c, ht;
-        if (BF) {  // e = (ht * 16 + c) * kp + k
-          k = e % pt.kp;
-          const int r = e / pt.kp;
-          c = r & 15;
-          ht = r >> 4;
-        } else {   // e = (ht * kp + k) * 16 + c
-          c = e & 15;
-          const int r = e >> 4;
-          k = r % pt.kp;
-          ht = r / pt.kp;
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(q0 + u * BT, total - 1);
+        const int jn = q % JR, k = (q / JR) % JR, h = q / PER_H;
+        const int t = jn >> 4, c = jn & 15;
+        v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
+        e[u] = BF ? ((h * NT + t) * 16 + c) * KP + k : ((h * NT + t) * KP + k) * 16 + c;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (q0 + u * BT < total) {
+          if (BF) TB16[e[u]] = bf16_bits(v[u]);
+          else TB[e[u]] = v[u];
         }
-        const int h = pt.nt == 1 ? ht : ht / pt.nt;
-        const int t = ht - h * pt.nt;
-        const int jn = 16 * t + c;
-        if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
       }
     }
+  } else {
+    if (zero_only) return;
+    const int total = pt.tb_len;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * BT) {
+      float v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * BT;
-      if (e < total) {
-        if (BF) TB16[e] = bf16_bits(v[u]);
-        else TB[e] = v[u];
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * BT;
+        v[u] = 0.f;
+        if (e < total) {
+          int k, c, ht;
+          if (BF) {  // e = (ht * 16 + c) * kp + k
+            k = e % pt.kp;
+            const int r = e / pt.kp;
+            c = r & 15;
+            ht = r >> 4;
+          } else {   // e = (ht * kp + k) * 16 + c
+            c = e & 15;
+            const int r = e >> 4;
+            k = r % pt.kp;
+            ht = r / pt.kp;
+          }
+          const int h = pt.nt == 1 ? ht : ht / pt.nt;
+          const int t = ht - h * pt.nt;
+          const int jn = 16 * t + c;
+          if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * BT;
+        if (e < total) {
+          if (BF) TB16[e] = bf16_bits(v[u]);
+          else TB[e] = v[u];
+        }
       }
     }
   }
@@ -397,6 +436,32 @@ __device__ __forceinline__ void build_hp(const PhaseTab& pt, const float* rowbuf
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (h0 + u < khi) hp[(h0 + u) * chp + p] = v[u];
+  }
+}
+
+// hp for two remaining modes and compile-time equal ranks: both rows of the
+// sample in registers, hp[(d1 + J d2) * chp + p] = row1[d1] row2[d2] (the
+// first remaining mode fastest, as in the maps).  The workgroup's threads
+// form BT / chp groups that split the d2 range.
+template <int JR, bool BF>
+__device__ __forceinline__ void build_hp2(const PhaseTab& pt, const float* rowbuf, int cnt, int chp, float* hp) {
+  const int G = blockDim.x / chp;
+  const int p = threadIdx.x % chp, g = threadIdx.x / chp;
+  if (g >= G) return;
+  float r1[JR], r2[JR];
+  read_row<JR, BF, true>(rowbuf, pt.c_hi, chp, p, JR, r1);
+  read_row<JR, BF, true>(rowbuf, pt.c_hi2, chp, p, JR, r2);
+  if (p >= cnt) {
+#pragma unroll
+    for (int j = 0; j < JR; ++j) r1[j] = 0.f;
+  }
+  for (int d2 = g; d2 < JR; d2 += G) {
+    float v2 = r2[0];
+#pragma unroll
+    for (int j = 1; j < JR; ++j)
+      if (j == d2) v2 = r2[j];
+#pragma unroll
+    for (int d1 = 0; d1 < JR; ++d1) hp[(d1 + JR * d2) * chp + p] = r1[d1] * v2;
   }
 }
 
@@ -763,6 +828,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     if (i < L.hm_len) hmap[i] = v;
     else tmap[i - L.hm_len] = v;
   }
+  if (!L.tb_all) build_table_arith<JR, BF, EXACT>(a.pt[1], Gs, hmap, TB, true);
   __syncthreads();
   if (L.tb_all) {
     for (int n = 0; n < N; ++n) {
@@ -888,7 +954,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
           build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
       }
-      if (!L.tb_all) build_table_arith<BF>(pt, Gs, hmap + pt.hm_off, TB);
+      if (!L.tb_all) build_table_arith<JR, BF, EXACT>(pt, Gs, hmap + pt.hm_off, TB);
 
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
@@ -926,7 +992,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       if constexpr (HPV) {
         hpr = HpRef<HPV, BF>{rowbuf, chp, pt.c_hi};
       } else {
-        build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
+        if (EXACT && pt.nhi == 2) build_hp2<JR, BF>(pt, rowbuf, cnt, chp, hp);
+        else build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
         hpr = HpRef<HPV, BF>{hp, chp, 0};
       }
       __syncthreads();
@@ -1173,6 +1240,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     t.c_n = L.coff[n];
     t.Jn = s.J[n];
     t.c_hi = q.nhi > 0 ? L.coff[q.hi[0]] : 0;
+    t.c_hi2 = q.nhi > 1 ? L.coff[q.hi[1]] : 0;
     t.tb_off = L.tb_all ? q.tb_off : 0;
     t.tb_len = q.tb_len;
     t.hm_off = q.hm_off;

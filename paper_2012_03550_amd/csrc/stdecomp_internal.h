@@ -59,6 +59,7 @@ struct PhaseTab {
   int jlo, kp, nt;
   int ls_n, ls_lo, Jn;
   int c_lo, c_n, c_hi;  // chunk offsets (ChainLayout::coff) of modes lo, n and the first remaining mode
+  int c_hi2;     // chunk offset of the second remaining mode (0 if none)
   int tb_off;    // element offset of mode n's table in the table region
   int tb_len;    // elements of mode n's table
   int hm_off;    // int offset of mode n's row-offset map

@@ -192,6 +192,7 @@ CASES = [
     ("n3_mixed_generic_w4", (60, 50, 40), (2, 3, 4), 3000, 32, 8, None),
     ("n2_uniform_w1", (80, 70), (4, 4), 4000, 64, 0, None),
     ("n4_uniform_w8", (30, 25, 20, 15), (3, 3, 3, 3), 5000, 128, 16, None),
+    ("n4_j8_tables_per_phase_w8", (60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 128, 1.2),
     ("n5_uniform", (12, 11, 10, 9, 8), (2, 2, 2, 2, 2), 3000, 64, 16, None),
     ("n3_zipf_long_runs_w8", (500, 400, 30), (4, 4, 4), 30000, 512, 64, 1.3),
     ("n3_j10_w4_ragged", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
