@@ -238,42 +238,75 @@ __device__ __forceinline__ void write_row(float* buf, int ck, int chp, int p, in
 // element e of slot sl at cbuf[e * 2W + sl], slot 2w the run that began
 // before chunk w, slot 2w+1 the run that goes on after it, elements [row,
 // count, partial sum (J), old master row (J)] (adjacent boundaries read
-// adjacent words).  Fills the LDS table `split` (row, then the new
-// master row at +4) in row order.  If `store`, also writes the rows (master,
-// and BF16 copy in BF16 mode).
+// adjacent words).  Fills the LDS table `split` (row, the run's first
+// boundary, then the new master row at +4) in row order.  If `store`, also
+// writes the rows (master, and BF16 copy in BF16 mode).
 template <int JR, bool EXACT, bool BF>
 __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
                                   const float* cbuf, float* split, int sstride, bool store) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = EXACT ? JR : a.s.J[pm];
+  const int NS = 2 * a.W;
+  // entry -> its first boundary (kept in the entry's header word 1)
   for (int bw = tid + 1; bw < a.W; bw += BT) {
     const int e = xn[bw];
-    if (e < 0) continue;
-    const int row = xr[bw];
-    const int NS = 2 * a.W;
-    const float* slotB = cbuf + (bw - 1) * 2 + 1;
+    if (e >= 0) split[e * sstride + 1] = __int_as_float(bw);
+  }
+  __syncthreads();
+  // A group of GL lanes per entry (GL = 4, or fewer when there are more
+  // entries than the workgroup has quads): lane i sums the before-slots of
+  // boundaries bw + i, bw + i + GL, ... of the run (a long run of a popular
+  // row crosses many chunks), then the group adds up by a fixed butterfly
+  // (quad DPP) and its first lane adds the after-slot of the chunk where the
+  // run began.
+  const int GL = nsplit * 4 <= BT ? 4 : (nsplit * 2 <= BT ? 2 : 1);
+  const int g = tid / GL, i = tid % GL, ng = BT / GL;
+  for (int e0 = 0; e0 < nsplit; e0 += ng) {
+    const int e = e0 + g;
+    const bool ok = e < nsplit;
+    const int bw = ok ? __float_as_int(split[e * sstride + 1]) : 1;
+    const int row = ok ? xr[bw] : -2;
     float F[JR];
-    int c = __float_as_int(slotB[NS]);
+    int c = 0;
 #pragma unroll
-    for (int j = 0; j < JR; ++j) F[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
-    for (int v = bw; v < a.W && xr[v] == row; ++v) {
+    for (int j = 0; j < JR; ++j) F[j] = 0.f;
+    for (int v = bw + i; ok && v < a.W && xr[v] == row; v += GL) {
       const float* slotA = cbuf + v * 2;
       c += __float_as_int(slotA[NS]);
 #pragma unroll
       for (int j = 0; j < JR; ++j)
         if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
     }
-    // (every LDS read before the first write: the compiler cannot tell the
-    // table from the slots and would otherwise order each read after it)
-    float old[JR];
+    if (GL >= 2) {  // lanes 2q, 2q+1 (and then the pairs of a quad): xor 1, then xor 2
+      c += __builtin_amdgcn_mov_dpp(c, 0xB1, 0xF, 0xF, false);
 #pragma unroll
-    for (int j = 0; j < JR; ++j) old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
-    float* ent = split + e * sstride;
-    ent[0] = __int_as_float(row);
-    const float inv_c = 1.0f / (float)c;
+      for (int j = 0; j < JR; ++j)
+        if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0xB1, 0xF, 0xF, false));
+      if (GL == 4) {
+        c += __builtin_amdgcn_mov_dpp(c, 0x4E, 0xF, 0xF, false);
 #pragma unroll
-    for (int j = 0; j < JR; ++j)
-      if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * (F[j] * inv_c + a.lA * old[j]);
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0x4E, 0xF, 0xF, false));
+      }
+    }
+    if (ok && i == 0) {
+      const float* slotB = cbuf + (bw - 1) * 2 + 1;
+      // (every LDS read before the first write: the compiler cannot tell the
+      // table from the slots and would otherwise order each read after it)
+      float old[JR], Fb[JR];
+      const int cb = __float_as_int(slotB[NS]);
+#pragma unroll
+      for (int j = 0; j < JR; ++j) {
+        Fb[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
+        old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
+      }
+      float* ent = split + e * sstride;
+      ent[0] = __int_as_float(row);
+      const float inv_c = 1.0f / (float)(c + cb);
+#pragma unroll
+      for (int j = 0; j < JR; ++j)
+        if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * ((Fb[j] + F[j]) * inv_c + a.lA * old[j]);
+    }
   }
   __syncthreads();
   if (store) {
@@ -400,19 +433,19 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
   }
 }
 
-// hp[h * chp + p] = prod over the remaining modes of the sample's rows at h
+// hp[h * hs + p] = prod over the remaining modes of the sample's rows at h
 // (1 when there are none); zero for positions p >= cnt.  hmap[khi + h * nhi + i]
 // is the position of remaining mode i's value at h in the row buffer less
 // the sample term (p * 4 floats, or p * 8 BF16 values).  Reads are batched
 // ahead of the writes, four h at a time.
 template <bool BF>
 __device__ __forceinline__ void build_hp(const PhaseTab& pt, const float* rowbuf, const int* hmap, int cnt, int chp,
-                                         float* hp) {
+                                         float* hp, int hs) {
   const int p = threadIdx.x;
   if (p >= chp) return;
   const int khi = pt.khi, nhi = pt.nhi;
   if (p >= cnt) {
-    for (int h = 0; h < khi; ++h) hp[h * chp + p] = 0.f;
+    for (int h = 0; h < khi; ++h) hp[h * hs + p] = 0.f;
     return;
   }
   if (nhi == 0) {
@@ -435,16 +468,17 @@ __device__ __forceinline__ void build_hp(const PhaseTab& pt, const float* rowbuf
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (h0 + u < khi) hp[(h0 + u) * chp + p] = v[u];
+      if (h0 + u < khi) hp[(h0 + u) * hs + p] = v[u];
   }
 }
 
 // hp for two remaining modes and compile-time equal ranks: both rows of the
-// sample in registers, hp[(d1 + J d2) * chp + p] = row1[d1] row2[d2] (the
+// sample in registers, hp[(d1 + J d2) * hs + p] = row1[d1] row2[d2] (the
 // first remaining mode fastest, as in the maps).  The workgroup's threads
 // form BT / chp groups that split the d2 range.
 template <int JR, bool BF>
-__device__ __forceinline__ void build_hp2(const PhaseTab& pt, const float* rowbuf, int cnt, int chp, float* hp) {
+__device__ __forceinline__ void build_hp2(const PhaseTab& pt, const float* rowbuf, int cnt, int chp, float* hp,
+                                          int hs) {
   const int G = blockDim.x / chp;
   const int p = threadIdx.x % chp, g = threadIdx.x / chp;
   if (g >= G) return;
@@ -461,7 +495,7 @@ __device__ __forceinline__ void build_hp2(const PhaseTab& pt, const float* rowbu
     for (int j = 1; j < JR; ++j)
       if (j == d2) v2 = r2[j];
 #pragma unroll
-    for (int d1 = 0; d1 < JR; ++d1) hp[(d1 + JR * d2) * chp + p] = r1[d1] * v2;
+    for (int d1 = 0; d1 < JR; ++d1) hp[(d1 + JR * d2) * hs + p] = r1[d1] * v2;
   }
 }
 
@@ -509,25 +543,25 @@ __device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int 
   }
 }
 
-// Where the products hp_p[h] are read from: the hp buffer (hp[h * chp + p]),
+// Where the products hp_p[h] are read from: the hp buffer (hp[h * hs + p]),
 // or, with a single remaining mode (three-mode tensors), that mode's rows in
 // the row buffer directly.
 template <bool HPV, bool BF>
 struct HpRef {
   const float* base;  // hp buffer, or the row buffer
-  int chp;
+  int st;             // hp buffer: its row stride; row buffer: chp
   int ck;             // (row buffer) chunk offset of the remaining mode
   __device__ __forceinline__ float one(int p, int h) const {
-    if constexpr (!HPV) return base[h * chp + p];
-    else return row_at<BF>(base, ck, chp, p, h);
+    if constexpr (!HPV) return base[h * st + p];
+    else return row_at<BF>(base, ck, st, p, h);
   }
   __device__ __forceinline__ f32x4 quad(int p, int h) const {  // samples p .. p+3
     if constexpr (!HPV) {
-      return *reinterpret_cast<const f32x4*>(base + h * chp + p);
+      return *reinterpret_cast<const f32x4*>(base + h * st + p);
     } else {
       f32x4 v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = row_at<BF>(base, ck, chp, p + i, h);
+      for (int i = 0; i < 4; ++i) v[i] = row_at<BF>(base, ck, st, p + i, h);
       return v;
     }
   }
@@ -568,42 +602,70 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
         a0[ks] = rowbuf[((clo + ks) * chp + prow0c) * 4 + kq];
         a1[ks] = TWO ? rowbuf[((clo + ks) * chp + prow1c) * 4 + kq] : 0.f;
       }
-      // One accumulation chain per tile and parity of h over K = (j_lo, h):
-      // the A operand is a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row),
-      // so the second stage folds into the MFMA chain.
+      // One accumulation chain per tile and K chunk ks (and parity of h when
+      // that gives fewer than four chains) over K = (j_lo, h): the A operand
+      // is a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
+      // stage folds into the MFMA chain, and consecutive MFMAs of a step go
+      // to different chains.
       const int nks = kp >> 2;
       const float* tb = TB + (t * kp + kq) * 16 + r16;
       const int hstride = nt * kp * 16;
-      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-      f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
-      auto step = [&](int h, f32x4& x0, f32x4& x1) {
-        const float hv0 = hpr.one(prow0c, h);
-        const float hv1 = TWO ? hpr.one(prow1c, h) : 0.f;
+      constexpr int PAR = TPJ * KS >= 4 ? 1 : 2;
+      f32x4 acc0[KS][PAR], acc1[KS][PAR];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < PAR; ++q) acc0[ks][q] = acc1[ks][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      auto mfmas = [&](int q, float hv0, float hv1, const float (&bv)[KS]) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           if (ks < nks) {
-            const float bv = tb[h * hstride + ks * 64];
-            x0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv, x0, 0, 0, 0);
-            if constexpr (TWO) x1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv, x1, 0, 0, 0);
+            acc0[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv[ks], acc0[ks][q], 0, 0, 0);
+            if constexpr (TWO) acc1[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv[ks], acc1[ks][q], 0, 0, 0);
           }
         }
       };
       if constexpr (KHI > 0) {  // trip count known: straight-line code, loads scheduled early
 #pragma unroll
-        for (int h = 0; h < KHI; h += 2) {
-          step(h, c0, c1);
-          if (h + 1 < KHI) step(h + 1, d0, d1);
+        for (int h = 0; h < KHI; ++h) {
+          float bv[KS];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) bv[ks] = ks < nks ? tb[h * hstride + ks * 64] : 0.f;
+          mfmas(h % PAR, hpr.one(prow0c, h), TWO ? hpr.one(prow1c, h) : 0.f, bv);
         }
       } else {
-        int h = 0;
-        for (; h + 1 < khi; h += 2) {
-          step(h, c0, c1);
-          step(h + 1, d0, d1);
+        // runtime trip count: h in pairs, the operands of the next pair read
+        // before the MFMAs of the current one (clamped reads stay in the
+        // buffers; a missing second h is skipped, uniformly for the wave)
+        struct Ops {
+          float hv0[2], hv1[2], bv[2][KS];
+        };
+        auto load = [&](int h, Ops& o) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int hh = min(h + u, khi - 1);
+            o.hv0[u] = hpr.one(prow0c, hh);
+            o.hv1[u] = TWO ? hpr.one(prow1c, hh) : 0.f;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) o.bv[u][ks] = ks < nks ? tb[hh * hstride + ks * 64] : 0.f;
+          }
+        };
+        Ops cur, nxt;
+        load(0, cur);
+        for (int h = 0; h < khi; h += 2) {
+          load(h + 2, nxt);
+          mfmas(0, cur.hv0[0], cur.hv1[0], cur.bv[0]);
+          if (h + 1 < khi) mfmas(PAR - 1, cur.hv0[1], cur.hv1[1], cur.bv[1]);
+          cur = nxt;
         }
-        if (h < khi) step(h, c0, c1);
       }
-      e0 = c0 + d0;
-      e1 = c1 + d1;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < PAR; ++q) {
+          e0 += acc0[ks][q];
+          if constexpr (TWO) e1 += acc1[ks][q];
+        }
     } else {
       constexpr int KS = (JR + 15) / 16;
       s16x4 a0[KS], a1[KS];
@@ -735,6 +797,91 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
       const int jra = 16 * t0a + 4 * kq + i, jrb = 16 * t0b + 4 * kq + i;
       if (jra < J0 && cola < ncol) out[jra + J0 * cola] = acca[i];
       if (has2 && jrb < J0 && colb < ncol) out[jrb + J0 * colb] = accb[i];
+    }
+  }
+}
+
+// The core gradient of a four-mode tensor with equal ranks, as one balanced
+// GEMM: rows (j0, j1) = j0 + J j1, columns h = (j2, j3) (the hp index),
+// dG[row, h] = sum_p (r_p a(0)_p[j0] a(1)_p[j1]) hp_p[h], K = the chunk's
+// samples; lin = row + J^2 h.  A wave takes one 16-row tile and up to four
+// 16-column tiles, so each A operand feeds four MFMA chains.
+template <int JR, bool BF>
+__device__ __forceinline__ void mfma_core_grad4(const PhaseTab& g, const float* rowbuf, const float* ra, int ras,
+                                                const float* hp, int hs, int cnt, int chp, float* out) {
+  constexpr int R = JR * JR;            // rows and columns
+  constexpr int T16 = (R + 15) / 16;    // tiles per side
+  constexpr int CG = T16 < 4 ? T16 : 4; // column tiles per job
+  constexpr int NCG = (T16 + CG - 1) / CG;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int clo = g.c_lo;
+  for (int job = wv; job < T16 * NCG; job += nwaves) {
+    const int rt = job / NCG, cg0 = (job - rt * NCG) * CG;
+    const int row = min(rt * 16 + r16, R - 1);
+    const int j0 = row % JR, j1 = row / JR;
+    int colc[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) colc[c] = min((cg0 + c) * 16 + r16, R - 1);
+    f32x4 acc[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (!BF) {
+      // K in groups of four steps (16 samples), the next group's operands
+      // read before the current group's MFMAs.  No masks: ra is zero for
+      // p >= cnt and every value read is finite.
+      const int ngroups = (cnt + 15) >> 4;
+      struct Ops {
+        float av[4], bv[4][CG];
+      };
+      auto load = [&](int gi, Ops& o) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = (4 * gi + u) * 4 + kq;
+          o.av[u] = ra[p * ras + j0] * rowbuf[((clo + (j1 >> 2)) * chp + p) * 4 + (j1 & 3)];
+#pragma unroll
+          for (int c = 0; c < CG; ++c) o.bv[u][c] = hp[colc[c] * hs + p];
+        }
+      };
+      Ops cur, nxt;
+      if (ngroups > 0) load(0, cur);
+      for (int gi = 0; gi < ngroups; ++gi) {
+        load(gi + 1 < ngroups ? gi + 1 : gi, nxt);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int c = 0; c < CG; ++c)
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.av[u], cur.bv[u][c], acc[c], 0, 0, 0);
+        }
+        cur = nxt;
+      }
+    } else {
+      const int nsteps = (cnt + 15) >> 4;  // 16 * nsteps <= chp
+      for (int st = 0; st < nsteps; ++st) {
+        const int p0 = st * 16 + 4 * kq;
+        s16x4 av;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          av[e] = (short)bf16_bits(ra[(p0 + e) * ras + j0] * row_at<BF>(rowbuf, clo, chp, p0 + e, j1));
+        s16x4 bv[CG];
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+          const f32x4 h4 = *reinterpret_cast<const f32x4*>(hp + colc[c] * hs + p0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) bv[c][e] = (short)bf16_bits(h4[e]);
+        }
+#pragma unroll
+        for (int c = 0; c < CG; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[c], acc[c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      const int col = (cg0 + c) * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rt * 16 + 4 * kq + i;
+        if (cg0 + c < T16 && r < R && col < R) out[r + R * col] = acc[c][i];
+      }
     }
   }
 }
@@ -890,10 +1037,19 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           }
           if (tid == 0) xc = xsrc[2 * a.W];
         }
-        if (ph == 1 && tid < P4) {
+        if (ph == 1 && !L.core2 && tid < P4) {
 #pragma unroll
           for (int v = 0; v < 8; ++v)
             if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
+        }
+        if (ph == 1 && L.core2) {  // this thread's share of the workgroup's slice
+          const int i = tid % L.cper, grp = tid / L.cper;
+          const int l4 = min(w * L.cper + i, P4 - 1);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int v = min(grp * L.cvg + u, a.W - 1);
+            if (u < L.cvg) pp[u] = psrc[(size_t)v * P4 + l4];
+          }
         }
         issue_rows_lds<JR, BF, EXACT, NM>(a, cur.idx, post, rowbuf, chp, active);
         if (splits) {
@@ -923,8 +1079,45 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       if (has_next) load_lane_rec<NM>(a, N, nbb, nph, nx);
       else nx.valid = false;
 
-      // ---- 2. core: finish the core step of this minibatch (same in every workgroup)
-      if (ph == 1) {
+      // ---- 2. core: finish the core step of this minibatch
+      if (ph == 1 && L.core2) {
+        // two levels: this workgroup's slice of G, one grid barrier, then all of G
+        f32x4* red = reinterpret_cast<f32x4*>(lds + L.red);
+        const int i = tid % L.cper, grp = tid / L.cper;
+        if (grp < L.cgrp) {
+          f32x4 sum = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (u < L.cvg && grp * L.cvg + u < a.W) sum += pp[u];
+          red[grp * L.cper + i] = sum;
+        }
+        __syncthreads();
+        const int l4 = w * L.cper + tid;
+        if (tid < L.cper && l4 < P4) {
+          f32x4 sum = {0.f, 0.f, 0.f, 0.f};
+          for (int g2 = 0; g2 < L.cgrp; ++g2) sum += red[g2 * L.cper + tid];
+          const float inv_m = 1.0f / (float)m;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int lin = 4 * l4 + e;
+            if (lin < P) a.G[lin] = Gs[lin] - a.gG * (-sum[e] * inv_m + a.lG * Gs[lin]);
+          }
+        }
+        passed += 1;
+        barrier_arrive(a, passed);
+        if (!barrier_wait(a, passed, misc + 7)) return;
+        for (int l4b = tid; l4b < P4; l4b += BT) {
+          float gv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) gv[e] = a.G[min(4 * l4b + e, P - 1)];
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (4 * l4b + e < P) Gs[4 * l4b + e] = gv[e];
+        }
+        __syncthreads();
+        if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
+          build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
+      } else if (ph == 1) {
         const float inv_m = 1.0f / (float)m;
         for (int l4 = tid; l4 < P4; l4 += BT) {
           f32x4 sum = {0.f, 0.f, 0.f, 0.f};
@@ -992,9 +1185,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       if constexpr (HPV) {
         hpr = HpRef<HPV, BF>{rowbuf, chp, pt.c_hi};
       } else {
-        if (EXACT && pt.nhi == 2) build_hp2<JR, BF>(pt, rowbuf, cnt, chp, hp);
-        else build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp);
-        hpr = HpRef<HPV, BF>{hp, chp, 0};
+        if (EXACT && pt.nhi == 2) build_hp2<JR, BF>(pt, rowbuf, cnt, chp, hp, L.hs);
+        else build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp, L.hs);
+        hpr = HpRef<HPV, BF>{hp, L.hs, 0};
       }
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
@@ -1023,7 +1216,10 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
         __syncthreads();
         // (the core-gradient tiles reuse hp of mode 0: the remaining modes of mode 1's columns)
-        mfma_core_grad<JR, BF, EXACT, HPV>(s, pt, rowbuf, rabuf, ras, hpr, cnt, chp, a.partial + (size_t)w * Pp);
+        if (!HPV && EXACT && pt.nhi == 2)
+          mfma_core_grad4<JR, BF>(pt, rowbuf, rabuf, ras, hp, L.hs, cnt, chp, a.partial + (size_t)w * Pp);
+        else
+          mfma_core_grad<JR, BF, EXACT, HPV>(s, pt, rowbuf, rabuf, ras, hpr, cnt, chp, a.partial + (size_t)w * Pp);
       } else {
         // ================= mode-n sub-step =================
         float u[JR], an[JR];
@@ -1179,6 +1375,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   auto tbf = [&](int len) { return bf ? (size_t)(len + 1) / 2 : (size_t)len; };
   ChainLayout& L = a.lay;
   L.chp = (a.chunk + 15) & ~15;
+  L.hs = L.chp + 4;
   {  // chunk-major row buffers: ceil(J_k / V) 16-byte chunks per mode and sample
     const int V = bf ? 8 : 4;
     int c = 0;
@@ -1193,7 +1390,18 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.ras = pad4(JR) + 1;
   L.sstride = 4 + pad4(JR);
   L.wstride = pad4(JR) + 4;
-  size_t common = al(s.P) + al(2 * (size_t)L.rowsz + kRowTail) + al((size_t)khimax * L.chp) + al((size_t)L.chp * L.es) +
+  {  // two-level core update when every workgroup summing all partials would cost more than a barrier
+    const int P4 = pad4(s.P) / 4;
+    const int per = (P4 + a.W - 1) / a.W;
+    const int grp = per <= threads ? threads / per : 0;
+    const int vg = grp > 0 ? (a.W + grp - 1) / grp : 0;
+    L.core2 = (a.W >= 8 && grp >= 1 && vg <= 8 && (long long)P4 * a.W >= 8192) ? 1 : 0;
+    L.cper = per;
+    L.cgrp = grp;
+    L.cvg = vg;
+  }
+  const size_t red_len = L.core2 ? (size_t)L.cgrp * L.cper * 4 : 0;
+  size_t common = al(red_len) + al(s.P) + al(2 * (size_t)L.rowsz + kRowTail) + al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) +
                   al((size_t)L.chp * L.ras) + al((size_t)a.split_cap * L.sstride) +
                   al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0) + al((size_t)hm_len) +
                   al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
@@ -1205,7 +1413,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.row0 = (int)off;  // (the two buffers are adjacent: one zero fill covers both and the tail)
   L.row1 = L.row0 + L.rowsz;
   off += al(2 * (size_t)L.rowsz + kRowTail);
-  L.hp = (int)off;    off += al((size_t)khimax * L.chp);
+  L.hp = (int)off;    off += al((size_t)khimax * L.hs);
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras);
   L.split = (int)off; off += al((size_t)a.split_cap * L.sstride);
@@ -1213,6 +1421,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.hmap = (int)off;  off += al((size_t)hm_len);
   L.tmap = (int)off;  off += L.tb_all ? al((size_t)tb_sum) : 0;
   L.wscr = (int)off;  off += al((size_t)(threads / 64) * L.wstride);
+  L.red = (int)off;   off += al(red_len);
   L.ints = (int)off;  off += 2 * (size_t)a.W + 8;
   L.total = (int)off;
   L.aux_len = hm_len + (L.tb_all ? tb_sum : 0);

@@ -33,11 +33,18 @@ struct Shape {
 struct ChainLayout {
   int gs, tb, row0, row1, hp, ebuf, ra, split, cbuf, hmap, tmap, wscr, ints, total;
   int chp;      // chunk rounded up to 16 (MFMA tile rows)
+  int hs;       // row stride of the hp buffer (chp + 4: lanes that read different h at one
+                // sample fall in different banks)
   int es;       // stride of the E buffer (odd)
   int ras;      // stride of the r * a(0) buffer
   int sstride;  // stride of the split-row table
   int wstride;  // stride of the per-wave scan tails
   int tb_all;   // 1: the tables of every mode stay resident (rebuilt once per minibatch)
+  // Two-level core update (large P * W): workgroup w reduces float4 columns
+  // [w * cper, (w + 1) * cper) of the partials in cgrp thread groups of cvg
+  // partials each (LDS region red, cgrp * cper float4), stores that slice of G,
+  // and after one more grid barrier every workgroup reads the whole new G.
+  int core2, red, cper, cgrp, cvg;
   int aux_len;  // ints of the host-built index maps (row-offset maps, then table gather maps)
   int hm_len;   // ints of the row-offset maps (the first part of aux)
   // Row buffers (two, alternating between sub-steps) are chunk-major: mode

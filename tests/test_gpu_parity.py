@@ -193,6 +193,7 @@ CASES = [
     ("n2_uniform_w1", (80, 70), (4, 4), 4000, 64, 0, None),
     ("n4_uniform_w8", (30, 25, 20, 15), (3, 3, 3, 3), 5000, 128, 16, None),
     ("n4_j8_tables_per_phase_w8", (60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 128, 1.2),
+    ("n4_j8_two_level_core_w16", (60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 64, 1.2),
     ("n5_uniform", (12, 11, 10, 9, 8), (2, 2, 2, 2, 2), 3000, 64, 16, None),
     ("n3_zipf_long_runs_w8", (500, 400, 30), (4, 4, 4), 30000, 512, 64, 1.3),
     ("n3_j10_w4_ragged", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
@@ -283,6 +284,7 @@ BF16_TOL = 1e-2
 BF_CASES = [
     ("bf16_n3_j10_w4", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
     ("bf16_n4_j8_w8", (40, 30, 20, 15), (8, 8, 8, 8), 8000, 512, 64, None),
+    ("bf16_n4_j8_w16", (40, 30, 20, 15), (8, 8, 8, 8), 8000, 1024, 64, 1.2),
     ("bf16_n3_mixed_generic", (60, 50, 40), (2, 3, 20), 3000, 64, 16, 1.3),
     ("bf16_n3_j16", (100, 90, 80), (16, 16, 16), 6000, 256, 64, None),
 ]
