@@ -977,6 +977,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   }
   if (!L.tb_all) build_table_arith<JR, BF, EXACT>(a.pt[1], Gs, hmap, TB, true);
   __syncthreads();
+  // (one table region: each phase's table is built in the previous phase's
+  // barrier window, the first here, and mode 0's after the core update)
+  if (!L.tb_all) build_table_arith<JR, BF, EXACT>(a.pt[0], Gs, hmap + a.pt[0].hm_off, TB);
   if (L.tb_all) {
     for (int n = 0; n < N; ++n) {
       const PhaseTab& q = a.pt[n + 1];
@@ -1147,7 +1150,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
           build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
       }
-      if (!L.tb_all) build_table_arith<JR, BF, EXACT>(pt, Gs, hmap + pt.hm_off, TB);
+      if (!L.tb_all && ph == 1) build_table_arith<JR, BF, EXACT>(pt, Gs, hmap + pt.hm_off, TB);
 
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
@@ -1294,8 +1297,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
       }
       // ---- 6. barrier: the next sub-step needs this one's result.  Between
-      //      arrival and wait: build the tables the core update changed (no
-      //      reads of what other workgroups write).
+      //      arrival and wait (no reads of what other workgroups write): build
+      //      the resident tables the core update changed, or, with one table
+      //      region, the next phase's table.
       passed += 1;
       barrier_arrive(a, passed);
       if (ph == 1 && L.tb_all) {
@@ -1304,6 +1308,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           build_table_map<BF>(Gs, tmap + q.tb_off, q.tb_len, BF ? TB + (q.tb_off >> 1) : TB + q.tb_off);
         }
       }
+      if (!L.tb_all && has_next && nph != 1)  // (this phase's contraction is done: the arrival synchronised)
+        build_table_arith<JR, BF, EXACT>(a.pt[nph], Gs, hmap + a.pt[nph].hm_off, TB);
       if (!barrier_wait(a, passed, misc + 7)) return;
       first = false;
       bsel ^= 1;
