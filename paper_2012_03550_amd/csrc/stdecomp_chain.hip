@@ -634,28 +634,32 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
           mfmas(h % PAR, hpr.one(prow0c, h), TWO ? hpr.one(prow1c, h) : 0.f, bv);
         }
       } else {
-        // runtime trip count: h in pairs, the operands of the next pair read
-        // before the MFMAs of the current one (clamped reads stay in the
-        // buffers; a missing second h is skipped, uniformly for the wave)
+        // runtime trip count: h in groups of four, the operands of the next
+        // group read before the MFMAs of the current one (clamped reads stay
+        // in the buffers; an h past the end gets a zero A operand)
+        constexpr int HG = 4;
         struct Ops {
-          float hv0[2], hv1[2], bv[2][KS];
+          float hv0[HG], hv1[HG], bv[HG][KS];
         };
-        auto load = [&](int h, Ops& o) {
+        auto load = [&](int h0, Ops& o) {
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int hh = min(h + u, khi - 1);
-            o.hv0[u] = hpr.one(prow0c, hh);
-            o.hv1[u] = TWO ? hpr.one(prow1c, hh) : 0.f;
+          for (int u = 0; u < HG; ++u) {
+            const int hc = min(h0 + u, khi - 1);
+            const bool live = h0 + u < khi;
+            const float x0 = hpr.one(prow0c, hc);
+            const float x1 = TWO ? hpr.one(prow1c, hc) : 0.f;
+            o.hv0[u] = live ? x0 : 0.f;
+            o.hv1[u] = live ? x1 : 0.f;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) o.bv[u][ks] = ks < nks ? tb[hh * hstride + ks * 64] : 0.f;
+            for (int ks = 0; ks < KS; ++ks) o.bv[u][ks] = ks < nks ? tb[hc * hstride + ks * 64] : 0.f;
           }
         };
         Ops cur, nxt;
         load(0, cur);
-        for (int h = 0; h < khi; h += 2) {
-          load(h + 2, nxt);
-          mfmas(0, cur.hv0[0], cur.hv1[0], cur.bv[0]);
-          if (h + 1 < khi) mfmas(PAR - 1, cur.hv0[1], cur.hv1[1], cur.bv[1]);
+        for (int h0 = 0; h0 < khi; h0 += HG) {
+          load(h0 + HG, nxt);
+#pragma unroll
+          for (int u = 0; u < HG; ++u) mfmas(u % PAR, cur.hv0[u], cur.hv1[u], cur.bv[u]);
           cur = nxt;
         }
       }
