@@ -31,6 +31,7 @@
 //   * the run structure of the (row, position) order (run starts, last
 //     positions, runs crossing chunk boundaries and their numbering) comes
 //     with the schedule, so the factor sub-step needs no search for it.
+#include <algorithm>
 #include <vector>
 
 #include "stdecomp_device.h"
@@ -38,6 +39,7 @@
 namespace stdk {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -320,11 +322,12 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
   }
 }
 
-// Tables of the two-stage contraction (B operand of stage 1), built from the
-// core Gs:
-//   FP32: TB[((h * nt + t) * kp + k) * 16 + c]   = G_(n)[16t + c, k + J_lo h]
-//   BF16: TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(same)
-// (zero outside j_n < J_n, k < J_lo).  With a host-built gather map (tmap[e]
+// Tables of the contraction (MFMA B operands), built from the core Gs:
+//   FP32, two-stage (TS): TB[(ct * ks2 + ks) * 64 + l] = G_(n)[j_n, k + J_lo h] with
+//         k = 2 ks + l / 32, l % 32 = j_n + J_n hh, h = ct * hpt + hh
+//   FP32, direct:         TB[((h * nt + t) * kp + k) * 16 + c] = G_(n)[16t + c, k + J_lo h]
+//   BF16: TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(G_(n)[16t + c, k + J_lo h])
+// (zero outside j_n < J_n, k < J_lo, hh < hpt, h < khi).  With a host-built gather map (tmap[e]
 // = offset in the core or -1) the build is one load and one store per element.
 template <bool BF>
 __device__ __forceinline__ void build_table_map(const float* Gs, const int* tmap, int len, float* TB) {
@@ -356,7 +359,7 @@ __device__ __forceinline__ void build_table_map(const float* Gs, const int* tmap
 // compile-time equal ranks every mode's table has its zero entries (k >= J_lo,
 // j_n >= J_n) in the same places, so they are written once at set-up
 // (zero_only) and each rebuild writes only the J_lo J_n khi core values.
-template <int JR, bool BF, bool EXACT>
+template <int JR, bool BF, bool EXACT, bool TS>
 __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const float* Gs, const int* hmap, float* TB,
                                                   bool zero_only = false) {
   unsigned short* TB16 = reinterpret_cast<unsigned short*>(TB);
@@ -381,9 +384,16 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
       for (int u = 0; u < 4; ++u) {
         const int q = min(q0 + u * BT, total - 1);
         const int jn = q % JR, k = (q / JR) % JR, h = q / PER_H;
-        const int t = jn >> 4, c = jn & 15;
         v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
-        e[u] = BF ? ((h * NT + t) * 16 + c) * KP + k : ((h * NT + t) * KP + k) * 16 + c;
+        if (BF) {
+          e[u] = ((h * NT + (jn >> 4)) * 16 + (jn & 15)) * KP + k;
+        } else if (!TS) {
+          e[u] = ((h * NT + (jn >> 4)) * KP + k) * 16 + (jn & 15);
+        } else {
+          constexpr int HPT = 32 / JR, KS2 = (JR + 1) / 2;
+          const int ct = h / HPT, hh = h - ct * HPT;
+          e[u] = (ct * KS2 + (k >> 1)) * 64 + ((k & 1) << 5) + hh * JR + jn;
+        }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -403,22 +413,30 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
         const int e = e0 + u * BT;
         v[u] = 0.f;
         if (e < total) {
-          int k, c, ht;
-          if (BF) {  // e = (ht * 16 + c) * kp + k
-            k = e % pt.kp;
-            const int r = e / pt.kp;
-            c = r & 15;
-            ht = r >> 4;
-          } else {   // e = (ht * kp + k) * 16 + c
-            c = e & 15;
-            const int r = e >> 4;
-            k = r % pt.kp;
-            ht = r / pt.kp;
+          if (!TS) {
+            int k, c, ht;
+            if (BF) {  // e = (ht * 16 + c) * kp + k
+              k = e % pt.kp;
+              const int r = e / pt.kp;
+              c = r & 15;
+              ht = r >> 4;
+            } else {   // e = (ht * kp + k) * 16 + c
+              c = e & 15;
+              const int r = e >> 4;
+              k = r % pt.kp;
+              ht = r / pt.kp;
+            }
+            const int h = pt.nt == 1 ? ht : ht / pt.nt;
+            const int t = ht - h * pt.nt;
+            const int jn = 16 * t + c;
+            if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
+          } else {   // e = (ct * ks2 + ks) * 64 + l, k = 2 ks + l / 32, column l % 32 = j_n + J_n hh
+            const int ct = e / (pt.ks2 * 64), r = e - ct * pt.ks2 * 64;
+            const int l = r & 63, k = 2 * (r >> 6) + (l >> 5), c = l & 31;
+            const int hh = c / pt.Jn, jn = c - hh * pt.Jn;
+            const int h = ct * pt.hpt + hh;
+            if (k < pt.jlo && hh < pt.hpt && h < pt.khi) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
           }
-          const int h = pt.nt == 1 ? ht : ht / pt.nt;
-          const int t = ht - h * pt.nt;
-          const int jn = 16 * t + c;
-          if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
         }
       }
 #pragma unroll
@@ -567,152 +585,247 @@ struct HpRef {
   }
 };
 
-// E_p for the chunk's samples into ebuf[p * es + j_n] (MFMA, see the file
-// header).  A job is TPJ 16-sample tiles (one, or two sharing the B loads)
-// times one 16-wide j_n tile; the caller picks TPJ = 1 when there are at
-// least as many waves as single-tile jobs.
+// E_p for the chunk's samples (MFMA, see the file header).
+//
+// FP32, three-mode kernels (HPV): one MFMA chain per 16-sample tile over
+// K = (j_lo, h), the A operand a(lo)_p[j_lo] hp_p[h] formed per lane, the B
+// operand the table of mode n (16 columns, j_n); E_p to ebuf[p * es + j_n].
+//
+// FP32, other kernels: two stages on 32x32x2 tiles.  Stage 1, per 32-sample block and
+// 32-column tile, C[p][(j_n, h)] = sum_{j_lo} a(lo)_p[j_lo] G_(n)[j_n, j_lo + J_lo h]
+// (K = J_lo in steps of 2, every column used: a tile holds hpt whole h);
+// stage 2, on the accumulators, S[p][j_n] += hp_p[h] C[p][(j_n, h)].  The
+// waves of a block share its column tiles; lane partial sums go to slot
+// (wave part, h mod hpt) of ebuf[p * es + slot * J_n + j_n] and the reader adds
+// the g.ens slots in order.
+//
+// BF16: a job is TPJ 16-sample tiles (one, or two sharing the B loads) times
+// one 16-wide j_n tile, C[p][j_n] per h on 16x16x16 BF16 MFMAs and the sum
+// over h on the accumulators; E_p goes to ebuf[p * es + j_n] (one slot).  The
+// caller picks TPJ = 1 when there are at least as many waves as single-tile
+// jobs (the FP32 three-mode path takes TPJ the same way).
 template <int JR, bool BF, bool EXACT, bool HPV, int KHI, int TPJ>
 __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const float* TB, const float* rowbuf,
                                        const HpRef<HPV, BF>& hpr, int cnt, int chp, float* ebuf, int es) {
-  constexpr bool TWO = TPJ == 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int r16 = lane & 15, kq = lane >> 4;
-  constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
   const int Jn = EXACT ? JR : g.Jn;
-  const int MT = (cnt + 15) >> 4;
   const int clo = g.c_lo;
   const int khi = g.khi;
-  const int kp = EXACT ? KPX : g.kp;
-  const int nt = EXACT ? (JR + 15) / 16 : g.nt;
-  const int jobs = ((MT + TPJ - 1) / TPJ) * nt;  // job = (tile group, j_n tile)
-  for (int job = wv; job < jobs; job += nwaves) {
-    const int mp = job / nt, t = job - mp * nt;
-    const int mt0 = TPJ * mp, mt1 = mt0 + 1;
-    const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
-    const int prow0c = min(prow0, chp - 1), prow1c = min(prow1, chp - 1);
-    f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (!BF) {
-      constexpr int KS = (JR + 3) / 4;
-      float a0[KS], a1[KS];
+  if constexpr (!BF && !HPV) {
+    constexpr int KSM = (JR + 1) / 2;        // K steps (upper bound when not EXACT)
+    const int ks2 = EXACT ? KSM : g.ks2;
+    const int hpt = EXACT ? 32 / JR : g.hpt;
+    const int ctn = g.ctn;
+    const int nblk = chp >> 5;                 // chp is a multiple of 32
+    const int nwb = max(1, nwaves / nblk);     // waves per block
+    const int c32 = lane & 31, khalf = lane >> 5;
+    const int hh = c32 / Jn, jj = c32 - hh * Jn;
+    const bool colok = hh < hpt;
+    for (int bj = wv; bj < nblk * nwb; bj += nwaves) {
+      const int blk = bj / nwb, wp = bj - blk * nwb;
+      if (blk * 32 >= cnt) continue;  // no live sample in the block (uniform)
+      // A operand: row 32 blk + c32 of the block, k = 2 ks + khalf of the lo-mode
+      // row (zero padding past J_lo; rows p >= cnt hold finite values that
+      // reach only samples that are not read)
+      float av[KSM];
+      const int pa = blk * 32 + c32;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        // no masks: the table rows k >= J_lo are zero, samples p >= cnt are
-        // not stored, and the row buffer holds finite values only.
-        // value k = 4 ks + kq of the lo-mode row: chunk ks, word kq
-        a0[ks] = rowbuf[((clo + ks) * chp + prow0c) * 4 + kq];
-        a1[ks] = TWO ? rowbuf[((clo + ks) * chp + prow1c) * 4 + kq] : 0.f;
+      for (int ks = 0; ks < KSM; ++ks) {
+        const int k = 2 * ks + khalf;
+        av[ks] = (EXACT || ks < ks2) ? rowbuf[((clo + (k >> 2)) * chp + pa) * 4 + (k & 3)] : 0.f;
       }
-      // One accumulation chain per tile and K chunk ks (and parity of h when
-      // that gives fewer than four chains) over K = (j_lo, h): the A operand
-      // is a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
-      // stage folds into the MFMA chain, and consecutive MFMAs of a step go
-      // to different chains.
-      const int nks = kp >> 2;
-      const float* tb = TB + (t * kp + kq) * 16 + r16;
-      const int hstride = nt * kp * 16;
-      constexpr int PAR = TPJ * KS >= 4 ? 1 : 2;
-      f32x4 acc0[KS][PAR], acc1[KS][PAR];
+      const int prow = blk * 32 + 4 * khalf;  // this lane's accumulator rows: prow + 8 q + i
+      float S[16];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+      for (int i = 0; i < 16; ++i) S[i] = 0.f;
+      constexpr int TT = 4;  // column tiles in flight (independent MFMA chains)
+      for (int ct0 = wp; ct0 < ctn; ct0 += TT * nwb) {
+        f32x16 acc[TT];
 #pragma unroll
-        for (int q = 0; q < PAR; ++q) acc0[ks][q] = acc1[ks][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      auto mfmas = [&](int q, float hv0, float hv1, const float (&bv)[KS]) {
+        for (int t = 0; t < TT; ++t)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (ks < nks) {
-            acc0[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv[ks], acc0[ks][q], 0, 0, 0);
-            if constexpr (TWO) acc1[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv[ks], acc1[ks][q], 0, 0, 0);
+          for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < KSM; ++ks) {
+          if (EXACT || ks < ks2) {
+            float bv[TT];
+#pragma unroll
+            for (int t = 0; t < TT; ++t) bv[t] = TB[(min(ct0 + t * nwb, ctn - 1) * ks2 + ks) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < TT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ks], bv[t], acc[t], 0, 0, 0);
           }
         }
-      };
-      if constexpr (KHI > 0) {  // trip count known: straight-line code, loads scheduled early
 #pragma unroll
-        for (int h = 0; h < KHI; ++h) {
-          float bv[KS];
+        for (int t = 0; t < TT; ++t) {
+          const int ct = ct0 + t * nwb;
+          const int h = ct * hpt + hh;
+          if (colok && ct < ctn && h < khi) {
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks) bv[ks] = ks < nks ? tb[h * hstride + ks * 64] : 0.f;
-          mfmas(h % PAR, hpr.one(prow0c, h), TWO ? hpr.one(prow1c, h) : 0.f, bv);
+            for (int q = 0; q < 4; ++q) {
+              const f32x4 hv = hpr.quad(prow + 8 * q, h);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) S[4 * q + i] = fmaf(hv[i], acc[t][4 * q + i], S[4 * q + i]);
+            }
+          }
         }
+      }
+      if (colok) {
+        const int slot = (wp * hpt + hh) * Jn + jj;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) ebuf[(prow + 8 * q + i) * es + slot] = S[4 * q + i];
+      }
+    }
+  } else {
+    constexpr bool TWO = TPJ == 2;
+    const int r16 = lane & 15, kq = lane >> 4;
+    constexpr int KPX = BF ? ((JR + 15) & ~15) : ((JR + 3) & ~3);
+    const int MT = (cnt + 15) >> 4;
+    const int kp = EXACT ? KPX : g.kp;
+    const int nt = EXACT ? (JR + 15) / 16 : g.nt;
+    const int jobs = ((MT + TPJ - 1) / TPJ) * nt;  // job = (tile group, j_n tile)
+    for (int job = wv; job < jobs; job += nwaves) {
+      const int mp = job / nt, t = job - mp * nt;
+      const int mt0 = TPJ * mp, mt1 = mt0 + 1;
+      const int prow0 = mt0 * 16 + r16, prow1 = mt1 * 16 + r16;
+      const int prow0c = min(prow0, chp - 1), prow1c = min(prow1, chp - 1);
+      f32x4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (!BF) {
+        constexpr int KS = (JR + 3) / 4;
+        float a0[KS], a1[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          // no masks: the table rows k >= J_lo are zero, samples p >= cnt are
+          // not stored, and the row buffer holds finite values only.
+          // value k = 4 ks + kq of the lo-mode row: chunk ks, word kq
+          a0[ks] = rowbuf[((clo + ks) * chp + prow0c) * 4 + kq];
+          a1[ks] = TWO ? rowbuf[((clo + ks) * chp + prow1c) * 4 + kq] : 0.f;
+        }
+        // One accumulation chain per tile and K chunk ks (and parity of h when
+        // that gives fewer than four chains) over K = (j_lo, h): the A operand
+        // is a(lo)_p[j_lo] * hp_p[h] (p = the lane's tile row), so the second
+        // stage folds into the MFMA chain, and consecutive MFMAs of a step go
+        // to different chains.
+        const int nks = kp >> 2;
+        const float* tb = TB + (t * kp + kq) * 16 + r16;
+        const int hstride = nt * kp * 16;
+        constexpr int PAR = TPJ * KS >= 4 ? 1 : 2;
+        f32x4 acc0[KS][PAR], acc1[KS][PAR];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int q = 0; q < PAR; ++q) acc0[ks][q] = acc1[ks][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        auto mfmas = [&](int q, float hv0, float hv1, const float (&bv)[KS]) {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            if (ks < nks) {
+              acc0[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks] * hv0, bv[ks], acc0[ks][q], 0, 0, 0);
+              if constexpr (TWO) acc1[ks][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks] * hv1, bv[ks], acc1[ks][q], 0, 0, 0);
+            }
+          }
+        };
+        if constexpr (KHI > 0) {  // trip count known: straight-line code, loads scheduled early
+#pragma unroll
+          for (int h = 0; h < KHI; ++h) {
+            float bv[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bv[ks] = ks < nks ? tb[h * hstride + ks * 64] : 0.f;
+            mfmas(h % PAR, hpr.one(prow0c, h), TWO ? hpr.one(prow1c, h) : 0.f, bv);
+          }
+        } else {
+          // runtime trip count: h in groups of four, the operands of the next
+          // group read before the MFMAs of the current one (clamped reads stay
+          // in the buffers; an h past the end gets a zero A operand)
+          constexpr int HG = 4;
+          struct Ops {
+            float hv0[HG], hv1[HG], bv[HG][KS];
+          };
+          auto load = [&](int h0, Ops& o) {
+#pragma unroll
+            for (int u = 0; u < HG; ++u) {
+              const int hc = min(h0 + u, khi - 1);
+              const bool live = h0 + u < khi;
+              const float x0 = hpr.one(prow0c, hc);
+              const float x1 = TWO ? hpr.one(prow1c, hc) : 0.f;
+              o.hv0[u] = live ? x0 : 0.f;
+              o.hv1[u] = live ? x1 : 0.f;
+#pragma unroll
+              for (int ks = 0; ks < KS; ++ks) o.bv[u][ks] = ks < nks ? tb[hc * hstride + ks * 64] : 0.f;
+            }
+          };
+          Ops cur, nxt;
+          load(0, cur);
+          for (int h0 = 0; h0 < khi; h0 += HG) {
+            load(h0 + HG, nxt);
+#pragma unroll
+            for (int u = 0; u < HG; ++u) mfmas(u % PAR, cur.hv0[u], cur.hv1[u], cur.bv[u]);
+            cur = nxt;
+          }
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int q = 0; q < PAR; ++q) {
+            e0 += acc0[ks][q];
+            if constexpr (TWO) e1 += acc1[ks][q];
+          }
       } else {
-        // runtime trip count: h in groups of four, the operands of the next
-        // group read before the MFMAs of the current one (clamped reads stay
-        // in the buffers; an h past the end gets a zero A operand)
-        constexpr int HG = 4;
-        struct Ops {
-          float hv0[HG], hv1[HG], bv[HG][KS];
-        };
-        auto load = [&](int h0, Ops& o) {
+          constexpr int KS = (JR + 15) / 16;
+          s16x4 a0[KS], a1[KS];
+          const unsigned short* b16 = reinterpret_cast<const unsigned short*>(rowbuf);
 #pragma unroll
-          for (int u = 0; u < HG; ++u) {
-            const int hc = min(h0 + u, khi - 1);
-            const bool live = h0 + u < khi;
-            const float x0 = hpr.one(prow0c, hc);
-            const float x1 = TWO ? hpr.one(prow1c, hc) : 0.f;
-            o.hv0[u] = live ? x0 : 0.f;
-            o.hv1[u] = live ? x1 : 0.f;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) o.bv[u][ks] = ks < nks ? tb[hc * hstride + ks * 64] : 0.f;
+          for (int ks = 0; ks < KS; ++ks) {
+            // values k = 16 ks + 4 kq + e (e < 4): chunk 2 ks + kq / 2, BF16 words 4 (kq & 1) + e
+            const int ch = clo + 2 * ks + (kq >> 1);
+            a0[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow0c) * 8 + 4 * (kq & 1));
+            if constexpr (TWO) a1[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow1c) * 8 + 4 * (kq & 1));
           }
-        };
-        Ops cur, nxt;
-        load(0, cur);
-        for (int h0 = 0; h0 < khi; h0 += HG) {
-          load(h0 + HG, nxt);
+          const int nks = kp >> 4;
+          const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * kp + 4 * kq;
+          const int hstride = nt * 16 * kp;
+          const int hq0 = mt0 * 16 + 4 * kq;
+          const int hq1 = min(mt1, MT - 1) * 16 + 4 * kq;  // (a missing tile mt1 is never stored)
+          for (int h = 0; h < khi; ++h) {
+            f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int u = 0; u < HG; ++u) mfmas(u % PAR, cur.hv0[u], cur.hv1[u], cur.bv[u]);
-          cur = nxt;
-        }
-      }
+            for (int ks = 0; ks < KS; ++ks) {
+              if (ks < nks) {
+                const s16x4 bv = *reinterpret_cast<const s16x4*>(tb + h * hstride + 16 * ks);
+                c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[ks], bv, c0, 0, 0, 0);
+                if constexpr (TWO) c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
+              }
+            }
+            const f32x4 h0 = hpr.quad(hq0, h);
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+            for (int i = 0; i < 4; ++i) e0[i] = fmaf(c0[i], h0[i], e0[i]);
+            if constexpr (TWO) {
+              const f32x4 h1 = hpr.quad(hq1, h);
 #pragma unroll
-        for (int q = 0; q < PAR; ++q) {
-          e0 += acc0[ks][q];
-          if constexpr (TWO) e1 += acc1[ks][q];
-        }
-    } else {
-      constexpr int KS = (JR + 15) / 16;
-      s16x4 a0[KS], a1[KS];
-      const unsigned short* b16 = reinterpret_cast<const unsigned short*>(rowbuf);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        // values k = 16 ks + 4 kq + e (e < 4): chunk 2 ks + kq / 2, BF16 words 4 (kq & 1) + e
-        const int ch = clo + 2 * ks + (kq >> 1);
-        a0[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow0c) * 8 + 4 * (kq & 1));
-        if constexpr (TWO) a1[ks] = *reinterpret_cast<const s16x4*>(b16 + (ch * chp + prow1c) * 8 + 4 * (kq & 1));
-      }
-      const int nks = kp >> 4;
-      const unsigned short* tb = reinterpret_cast<const unsigned short*>(TB) + (t * 16 + r16) * kp + 4 * kq;
-      const int hstride = nt * 16 * kp;
-      const int hq0 = mt0 * 16 + 4 * kq;
-      const int hq1 = min(mt1, MT - 1) * 16 + 4 * kq;  // (a missing tile mt1 is never stored)
-      for (int h = 0; h < khi; ++h) {
-        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (ks < nks) {
-            const s16x4 bv = *reinterpret_cast<const s16x4*>(tb + h * hstride + 16 * ks);
-            c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[ks], bv, c0, 0, 0, 0);
-            if constexpr (TWO) c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[ks], bv, c1, 0, 0, 0);
+              for (int i = 0; i < 4; ++i) e1[i] = fmaf(c1[i], h1[i], e1[i]);
+            }
           }
-        }
-        const f32x4 h0 = hpr.quad(hq0, h);
+      }
+      const int jn = 16 * t + r16;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) e0[i] = fmaf(c0[i], h0[i], e0[i]);
-        if constexpr (TWO) {
-          const f32x4 h1 = hpr.quad(hq1, h);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) e1[i] = fmaf(c1[i], h1[i], e1[i]);
-        }
+      for (int i = 0; i < 4; ++i) {
+        const int p0 = mt0 * 16 + 4 * kq + i, p1 = mt1 * 16 + 4 * kq + i;
+        if (p0 < cnt && jn < Jn) ebuf[p0 * es + jn] = e0[i];
+        if (TWO && p1 < cnt && jn < Jn) ebuf[p1 * es + jn] = e1[i];
       }
     }
-    const int jn = 16 * t + r16;
+  }
+}
+
+// E_p[j] of one sample: the sum of its ens partial slots in slot order.
+template <int JR, bool EXACT>
+__device__ __forceinline__ void read_e(const float* eb, int ens, int Jn, float (&ev)[JR]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p0 = mt0 * 16 + 4 * kq + i, p1 = mt1 * 16 + 4 * kq + i;
-      if (p0 < cnt && jn < Jn) ebuf[p0 * es + jn] = e0[i];
-      if (TWO && p1 < cnt && jn < Jn) ebuf[p1 * es + jn] = e1[i];
-    }
+  for (int j = 0; j < JR; ++j) ev[j] = (EXACT || j < Jn) ? eb[j] : 0.f;
+  for (int sl = 1; sl < ens; ++sl) {
+#pragma unroll
+    for (int j = 0; j < JR; ++j)
+      if (EXACT || j < Jn) ev[j] += eb[sl * Jn + j];
   }
 }
 
@@ -936,6 +1049,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
   constexpr bool BF = BFI != 0;
+  constexpr bool TS = !BF && NU != 3;  // two-stage FP32 contraction (layout of the tables)
   extern __shared__ float lds[];
   const Shape& s = a.s;
   const int N = NU ? NU : s.N;
@@ -979,11 +1093,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     if (i < L.hm_len) hmap[i] = v;
     else tmap[i - L.hm_len] = v;
   }
-  if (!L.tb_all) build_table_arith<JR, BF, EXACT>(a.pt[1], Gs, hmap, TB, true);
+  if (!L.tb_all) build_table_arith<JR, BF, EXACT, TS>(a.pt[1], Gs, hmap, TB, true);
   __syncthreads();
   // (one table region: each phase's table is built in the previous phase's
   // barrier window, the first here, and mode 0's after the core update)
-  if (!L.tb_all) build_table_arith<JR, BF, EXACT>(a.pt[0], Gs, hmap + a.pt[0].hm_off, TB);
+  if (!L.tb_all) build_table_arith<JR, BF, EXACT, TS>(a.pt[0], Gs, hmap + a.pt[0].hm_off, TB);
   if (L.tb_all) {
     for (int n = 0; n < N; ++n) {
       const PhaseTab& q = a.pt[n + 1];
@@ -1154,7 +1268,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
           build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
       }
-      if (!L.tb_all && ph == 1) build_table_arith<JR, BF, EXACT>(pt, Gs, hmap + pt.hm_off, TB);
+      if (!L.tb_all && ph == 1) build_table_arith<JR, BF, EXACT, TS>(pt, Gs, hmap + pt.hm_off, TB);
 
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
@@ -1199,10 +1313,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
       constexpr int KHI = (EXACT && NU == 3) ? JR : 0;  // h trip count of three-mode equal-rank kernels
-      if (((cnt + 15) >> 4) * pt.nt <= (BT >> 6))  // enough waves for one tile each
+      if constexpr (!BF && !HPV) {
         mfma_E<JR, BF, EXACT, HPV, KHI, 1>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
-      else
-        mfma_E<JR, BF, EXACT, HPV, KHI, 2>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+      } else {
+        if (((cnt + 15) >> 4) * pt.nt <= (BT >> 6))  // enough waves for one tile each
+          mfma_E<JR, BF, EXACT, HPV, KHI, 1>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+        else
+          mfma_E<JR, BF, EXACT, HPV, KHI, 2>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
+      }
       __syncthreads();
 
       if (ph == 0) {
@@ -1211,10 +1329,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           float r = 0.f, a0r[JR];
           read_row<JR, BF, EXACT>(rowbuf, pt.c_n, chp, min(tid, chp - 1), Jn, a0r);
           if (active) {
+            float ev[JR];
+            read_e<JR, EXACT>(ebuf + tid * es, pt.ens, Jn, ev);
             float xh = 0.f;
 #pragma unroll
             for (int j = 0; j < JR; ++j)
-              if (EXACT || j < Jn) xh = fmaf(a0r[j], ebuf[tid * es + j], xh);
+              if (EXACT || j < Jn) xh = fmaf(a0r[j], ev[j], xh);
             r = cur.x - xh;
           }
 #pragma unroll
@@ -1233,12 +1353,13 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
 #pragma unroll
         for (int j = 0; j < JR; ++j) u[j] = an[j] = 0.f;
         if (active) {
-          float xh = 0.f, av[JR];
+          float xh = 0.f, av[JR], ev[JR];
           read_row<JR, BF, EXACT>(rowbuf, pt.c_n, chp, tid, Jn, av);
+          read_e<JR, EXACT>(ebuf + tid * es, pt.ens, Jn, ev);
 #pragma unroll
           for (int j = 0; j < JR; ++j) {
             if (EXACT || j < Jn) {
-              const float e = ebuf[tid * es + j];
+              const float e = ev[j];
               an[j] = BF ? an_cur[j] : av[j];
               xh = fmaf(av[j], e, xh);
               u[j] = e;
@@ -1313,7 +1434,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
         }
       }
       if (!L.tb_all && has_next && nph != 1)  // (this phase's contraction is done: the arrival synchronised)
-        build_table_arith<JR, BF, EXACT>(a.pt[nph], Gs, hmap + a.pt[nph].hm_off, TB);
+        build_table_arith<JR, BF, EXACT, TS>(a.pt[nph], Gs, hmap + a.pt[nph].hm_off, TB);
       if (!barrier_wait(a, passed, misc + 7)) return;
       first = false;
       bsel ^= 1;
@@ -1358,8 +1479,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   struct ModeT {
     int lo, nhi, khi, jlo, kp, nt, hi[kMaxOrder];
     int hm_off, tb_off, tb_len;
+    int ks2, hpt, ctn;
   } mt[kMaxOrder];
   int jmax = 0, hm_len = 0, tb_sum = 0, tb_max = 0, khimax = 1;
+  const bool ts = !bf && N != 3;  // the FP32 contraction of the kernels for N != 3 is two-stage
   for (int n = 0; n < N; ++n) {
     ModeT& q = mt[n];
     jmax = s.J[n] > jmax ? s.J[n] : jmax;
@@ -1374,7 +1497,12 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     q.jlo = s.J[q.lo];
     q.kp = bf ? ((q.jlo + 15) & ~15) : pad4(q.jlo);
     q.nt = (s.J[n] + 15) / 16;
-    q.tb_len = q.khi * q.nt * q.kp * 16;
+    q.ks2 = (q.jlo + 1) / 2;
+    q.hpt = 32 / s.J[n];
+    q.ctn = (q.khi + q.hpt - 1) / q.hpt;
+    // BF16: [h][j_n tile][16 j_n][kp k]; FP32 three-mode: [h][j_n tile][kp k][16 j_n];
+    // FP32 otherwise (two-stage): [column tile][K step][64 lanes]
+    q.tb_len = ts ? q.ctn * q.ks2 * 64 : q.khi * q.nt * q.kp * 16;
     q.hm_off = hm_len;
     hm_len += q.khi * (1 + q.nhi);
     q.tb_off = tb_sum;
@@ -1384,7 +1512,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   }
   auto tbf = [&](int len) { return bf ? (size_t)(len + 1) / 2 : (size_t)len; };
   ChainLayout& L = a.lay;
-  L.chp = (a.chunk + 15) & ~15;
+  L.chp = (a.chunk + 31) & ~31;
   L.hs = L.chp + 4;
   {  // chunk-major row buffers: ceil(J_k / V) 16-byte chunks per mode and sample
     const int V = bf ? 8 : 4;
@@ -1396,7 +1524,16 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     L.ctot = c;
     L.rowsz = L.ctot * L.chp * 4;
   }
-  L.es = 16 * ((jmax + 15) / 16) + 1;
+  // waves per 32-sample block in the FP32 contraction, each with its own
+  // partial-E slots
+  const int nwb = std::max(1, (threads / 64) / ((L.chp + 31) / 32));
+  if (!ts) {
+    L.es = 16 * ((jmax + 15) / 16) + 1;
+  } else {
+    int e = 1;
+    for (int n = 0; n < N; ++n) e = std::max(e, nwb * mt[n].hpt * s.J[n]);
+    L.es = e + 1 + (e & 1);  // odd, > e
+  }
   L.ras = pad4(JR) + 1;
   L.sstride = 4 + pad4(JR);
   L.wstride = pad4(JR) + 4;
@@ -1464,6 +1601,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     t.tb_len = q.tb_len;
     t.hm_off = q.hm_off;
     t.tm_off = t.tb_off;
+    t.ks2 = q.ks2;
+    t.hpt = q.hpt;
+    t.ctn = q.ctn;
+    t.ens = ts ? nwb * q.hpt : 1;
   }
   for (int ph = N + 1; ph <= kMaxOrder; ++ph) a.pt[ph] = PhaseTab{};
 
@@ -1491,21 +1632,30 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
       if (L.tb_all) {
         int* tm = aux + hm_len + q.tb_off;
         for (int e = 0; e < q.tb_len; ++e) {
-          int k, c, ht;
-          if (bf) {
-            k = e % q.kp;
-            const int r = e / q.kp;
-            c = r & 15;
-            ht = r >> 4;
+          if (!ts) {
+            int k, c, ht;
+            if (bf) {
+              k = e % q.kp;
+              const int r = e / q.kp;
+              c = r & 15;
+              ht = r >> 4;
+            } else {
+              c = e & 15;
+              const int r = e >> 4;
+              k = r % q.kp;
+              ht = r / q.kp;
+            }
+            const int h = ht / q.nt, t = ht - h * q.nt;
+            const int jn = 16 * t + c;
+            tm[e] = (k < q.jlo && jn < s.J[n]) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
           } else {
-            c = e & 15;
-            const int r = e >> 4;
-            k = r % q.kp;
-            ht = r / q.kp;
+            const int ct = e / (q.ks2 * 64), r = e - ct * q.ks2 * 64;
+            const int ks = r >> 6, l = r & 63;
+            const int k = 2 * ks + (l >> 5), c = l & 31;
+            const int hh = c / s.J[n], jn = c - hh * s.J[n];
+            const int h = ct * q.hpt + hh;
+            tm[e] = (k < q.jlo && hh < q.hpt && h < q.khi) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
           }
-          const int h = ht / q.nt, t = ht - h * q.nt;
-          const int jn = 16 * t + c;
-          tm[e] = (k < q.jlo && jn < s.J[n]) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
         }
       }
     }

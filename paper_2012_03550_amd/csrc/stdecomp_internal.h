@@ -32,7 +32,7 @@ struct Shape {
 // LDS regions of a chain workgroup (float offsets) and strides.
 struct ChainLayout {
   int gs, tb, row0, row1, hp, ebuf, ra, split, cbuf, hmap, tmap, wscr, ints, total;
-  int chp;      // chunk rounded up to 16 (MFMA tile rows)
+  int chp;      // chunk rounded up to 32 (MFMA tile rows)
   int hs;       // row stride of the hp buffer (chp + 4: lanes that read different h at one
                 // sample fall in different banks)
   int es;       // stride of the E buffer (odd)
@@ -71,6 +71,10 @@ struct PhaseTab {
   int tb_len;    // elements of mode n's table
   int hm_off;    // int offset of mode n's row-offset map
   int tm_off;    // int offset of mode n's table gather map (resident tables only)
+  // FP32 contraction (32x32 tiles, K = j_lo in steps of 2): ks2 K steps,
+  // hpt multi-indices h per 32-column tile (columns j_n + J_n * (h mod hpt)),
+  // ctn column tiles, ens partial-E slots per sample in the E buffer
+  int ks2, hpt, ctn, ens;
 };
 
 // Schedule words per (minibatch, mode) in the chunk-boundary array:
