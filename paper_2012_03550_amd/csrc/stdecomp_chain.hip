@@ -325,8 +325,10 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
 // Tables of the contraction (MFMA B operands), built from the core Gs:
 //   FP32, two-stage (TS): TB[(ct * ks2 + ks) * 64 + l] = G_(n)[j_n, k + J_lo h] with
 //         k = 2 ks + l / 32, l % 32 = j_n + J_n hh, h = ct * hpt + hh
+//   BF16, two-stage:      TB16[((ct * ks2 + ks) * 64 + l) * 4 + i] = bf16(same) with
+//         k = 8 ks + 4 (l / 32) + i
 //   FP32, direct:         TB[((h * nt + t) * kp + k) * 16 + c] = G_(n)[16t + c, k + J_lo h]
-//   BF16: TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(G_(n)[16t + c, k + J_lo h])
+//   BF16, direct:         TB16[((h * nt + t) * 16 + c) * kp + k] = bf16(G_(n)[16t + c, k + J_lo h])
 // (zero outside j_n < J_n, k < J_lo, hh < hpt, h < khi).  With a host-built gather map (tmap[e]
 // = offset in the core or -1) the build is one load and one store per element.
 template <bool BF>
@@ -385,8 +387,12 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
         const int q = min(q0 + u * BT, total - 1);
         const int jn = q % JR, k = (q / JR) % JR, h = q / PER_H;
         v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
-        if (BF) {
+        if (BF && !TS) {
           e[u] = ((h * NT + (jn >> 4)) * 16 + (jn & 15)) * KP + k;
+        } else if (BF) {
+          constexpr int HPT = 32 / JR, KS8 = (JR + 7) / 8;
+          const int ct = h / HPT, hh = h - ct * HPT;
+          e[u] = ((ct * KS8 + (k >> 3)) * 64 + (((k >> 2) & 1) << 5) + hh * JR + jn) * 4 + (k & 3);
         } else if (!TS) {
           e[u] = ((h * NT + (jn >> 4)) * KP + k) * 16 + (jn & 15);
         } else {
@@ -430,9 +436,11 @@ __device__ __forceinline__ void build_table_arith(const PhaseTab& pt, const floa
             const int t = ht - h * pt.nt;
             const int jn = 16 * t + c;
             if (k < pt.jlo && jn < pt.Jn) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
-          } else {   // e = (ct * ks2 + ks) * 64 + l, k = 2 ks + l / 32, column l % 32 = j_n + J_n hh
-            const int ct = e / (pt.ks2 * 64), r = e - ct * pt.ks2 * 64;
-            const int l = r & 63, k = 2 * (r >> 6) + (l >> 5), c = l & 31;
+          } else {   // e = ((ct * ks2 + ks) * 64 + l) * lw + ee, column l % 32 = j_n + J_n hh
+            const int lw = BF ? 4 : 1;
+            const int ct = e / (pt.ks2 * 64 * lw), r = e - ct * pt.ks2 * 64 * lw;
+            const int l = (r / lw) & 63, ks = r / (64 * lw), ee = r % lw;
+            const int k = BF ? 8 * ks + 4 * (l >> 5) + ee : 2 * ks + (l >> 5), c = l & 31;
             const int hh = c / pt.Jn, jn = c - hh * pt.Jn;
             const int h = ct * pt.hpt + hh;
             if (k < pt.jlo && hh < pt.hpt && h < pt.khi) v[u] = Gs[hmap[h] + k * pt.ls_lo + jn * pt.ls_n];
@@ -591,15 +599,15 @@ struct HpRef {
 // K = (j_lo, h), the A operand a(lo)_p[j_lo] hp_p[h] formed per lane, the B
 // operand the table of mode n (16 columns, j_n); E_p to ebuf[p * es + j_n].
 //
-// FP32, other kernels: two stages on 32x32x2 tiles.  Stage 1, per 32-sample block and
+// Other kernels: two stages on 32x32 tiles (FP32 32x32x2, BF16 32x32x8).  Stage 1, per 32-sample block and
 // 32-column tile, C[p][(j_n, h)] = sum_{j_lo} a(lo)_p[j_lo] G_(n)[j_n, j_lo + J_lo h]
-// (K = J_lo in steps of 2, every column used: a tile holds hpt whole h);
+// (K = J_lo in steps of 2 or 8, every column used: a tile holds hpt whole h);
 // stage 2, on the accumulators, S[p][j_n] += hp_p[h] C[p][(j_n, h)].  The
 // waves of a block share its column tiles; lane partial sums go to slot
 // (wave part, h mod hpt) of ebuf[p * es + slot * J_n + j_n] and the reader adds
 // the g.ens slots in order.
 //
-// BF16: a job is TPJ 16-sample tiles (one, or two sharing the B loads) times
+// BF16, three-mode kernels: a job is TPJ 16-sample tiles (one, or two sharing the B loads) times
 // one 16-wide j_n tile, C[p][j_n] per h on 16x16x16 BF16 MFMAs and the sum
 // over h on the accumulators; E_p goes to ebuf[p * es + j_n] (one slot).  The
 // caller picks TPJ = 1 when there are at least as many waves as single-tile
@@ -611,8 +619,8 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
   const int Jn = EXACT ? JR : g.Jn;
   const int clo = g.c_lo;
   const int khi = g.khi;
-  if constexpr (!BF && !HPV) {
-    constexpr int KSM = (JR + 1) / 2;        // K steps (upper bound when not EXACT)
+  if constexpr (!HPV) {
+    constexpr int KSM = BF ? (JR + 7) / 8 : (JR + 1) / 2;  // K steps (upper bound when not EXACT)
     const int ks2 = EXACT ? KSM : g.ks2;
     const int hpt = EXACT ? 32 / JR : g.hpt;
     const int ctn = g.ctn;
@@ -628,11 +636,18 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
       // row (zero padding past J_lo; rows p >= cnt hold finite values that
       // reach only samples that are not read)
       float av[KSM];
+      s16x4 avb[KSM];
       const int pa = blk * 32 + c32;
 #pragma unroll
       for (int ks = 0; ks < KSM; ++ks) {
-        const int k = 2 * ks + khalf;
-        av[ks] = (EXACT || ks < ks2) ? rowbuf[((clo + (k >> 2)) * chp + pa) * 4 + (k & 3)] : 0.f;
+        if constexpr (!BF) {
+          const int k = 2 * ks + khalf;
+          av[ks] = (EXACT || ks < ks2) ? rowbuf[((clo + (k >> 2)) * chp + pa) * 4 + (k & 3)] : 0.f;
+        } else {  // k = 8 ks + 4 khalf + i: chunk ks, BF16 words 4 khalf + i
+          const unsigned short* b16 = reinterpret_cast<const unsigned short*>(rowbuf);
+          avb[ks] = (EXACT || ks < ks2) ? *reinterpret_cast<const s16x4*>(b16 + ((clo + ks) * chp + pa) * 8 + 4 * khalf)
+                                        : s16x4{0, 0, 0, 0};
+        }
       }
       const int prow = blk * 32 + 4 * khalf;  // this lane's accumulator rows: prow + 8 q + i
       float S[16];
@@ -648,11 +663,21 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks) {
           if (EXACT || ks < ks2) {
-            float bv[TT];
+            if constexpr (!BF) {
+              float bv[TT];
 #pragma unroll
-            for (int t = 0; t < TT; ++t) bv[t] = TB[(min(ct0 + t * nwb, ctn - 1) * ks2 + ks) * 64 + lane];
+              for (int t = 0; t < TT; ++t) bv[t] = TB[(min(ct0 + t * nwb, ctn - 1) * ks2 + ks) * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < TT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ks], bv[t], acc[t], 0, 0, 0);
+              for (int t = 0; t < TT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ks], bv[t], acc[t], 0, 0, 0);
+            } else {
+              const unsigned short* tb16 = reinterpret_cast<const unsigned short*>(TB);
+              s16x4 bv[TT];
+#pragma unroll
+              for (int t = 0; t < TT; ++t)
+                bv[t] = *reinterpret_cast<const s16x4*>(tb16 + ((min(ct0 + t * nwb, ctn - 1) * ks2 + ks) * 64 + lane) * 4);
+#pragma unroll
+              for (int t = 0; t < TT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(avb[ks], bv[t], acc[t], 0, 0, 0);
+            }
           }
         }
 #pragma unroll
@@ -1049,7 +1074,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
   constexpr bool BF = BFI != 0;
-  constexpr bool TS = !BF && NU != 3;  // two-stage FP32 contraction (layout of the tables)
+  constexpr bool TS = NU != 3;  // two-stage contraction (layout of the tables)
   extern __shared__ float lds[];
   const Shape& s = a.s;
   const int N = NU ? NU : s.N;
@@ -1313,7 +1338,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       __syncthreads();
       const float* TBn = L.tb_all ? (BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off) : TB;
       constexpr int KHI = (EXACT && NU == 3) ? JR : 0;  // h trip count of three-mode equal-rank kernels
-      if constexpr (!BF && !HPV) {
+      if constexpr (!HPV) {
         mfma_E<JR, BF, EXACT, HPV, KHI, 1>(s, pt, TBn, rowbuf, hpr, cnt, chp, ebuf, es);
       } else {
         if (((cnt + 15) >> 4) * pt.nt <= (BT >> 6))  // enough waves for one tile each
@@ -1482,7 +1507,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     int ks2, hpt, ctn;
   } mt[kMaxOrder];
   int jmax = 0, hm_len = 0, tb_sum = 0, tb_max = 0, khimax = 1;
-  const bool ts = !bf && N != 3;  // the FP32 contraction of the kernels for N != 3 is two-stage
+  const bool ts = N != 3;  // the contraction of the kernels for N != 3 is two-stage (32x32 tiles)
   for (int n = 0; n < N; ++n) {
     ModeT& q = mt[n];
     jmax = s.J[n] > jmax ? s.J[n] : jmax;
@@ -1497,12 +1522,12 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     q.jlo = s.J[q.lo];
     q.kp = bf ? ((q.jlo + 15) & ~15) : pad4(q.jlo);
     q.nt = (s.J[n] + 15) / 16;
-    q.ks2 = (q.jlo + 1) / 2;
+    q.ks2 = bf ? (q.jlo + 7) / 8 : (q.jlo + 1) / 2;  // K steps of 8 (BF16) or 2 (FP32)
     q.hpt = 32 / s.J[n];
     q.ctn = (q.khi + q.hpt - 1) / q.hpt;
-    // BF16: [h][j_n tile][16 j_n][kp k]; FP32 three-mode: [h][j_n tile][kp k][16 j_n];
-    // FP32 otherwise (two-stage): [column tile][K step][64 lanes]
-    q.tb_len = ts ? q.ctn * q.ks2 * 64 : q.khi * q.nt * q.kp * 16;
+    // three-mode, BF16: [h][j_n tile][16 j_n][kp k]; FP32: [h][j_n tile][kp k][16 j_n];
+    // two-stage: [column tile][K step][64 lanes] (BF16: 4 values per lane)
+    q.tb_len = ts ? q.ctn * q.ks2 * 64 * (bf ? 4 : 1) : q.khi * q.nt * q.kp * 16;
     q.hm_off = hm_len;
     hm_len += q.khi * (1 + q.nhi);
     q.tb_off = tb_sum;
@@ -1649,9 +1674,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
             const int jn = 16 * t + c;
             tm[e] = (k < q.jlo && jn < s.J[n]) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
           } else {
-            const int ct = e / (q.ks2 * 64), r = e - ct * q.ks2 * 64;
-            const int ks = r >> 6, l = r & 63;
-            const int k = 2 * ks + (l >> 5), c = l & 31;
+            const int lw = bf ? 4 : 1;  // values per lane
+            const int ct = e / (q.ks2 * 64 * lw), r = e - ct * q.ks2 * 64 * lw;
+            const int ks = r / (64 * lw), l = (r / lw) & 63, ee = r % lw;
+            const int k = bf ? 8 * ks + 4 * (l >> 5) + ee : 2 * ks + (l >> 5), c = l & 31;
             const int hh = c / s.J[n], jn = c - hh * s.J[n];
             const int h = ct * q.hpt + hh;
             tm[e] = (k < q.jlo && hh < q.hpt && h < q.khi) ? hoff[h] + k * s.lstride[q.lo] + jn * s.lstride[n] : -1;
