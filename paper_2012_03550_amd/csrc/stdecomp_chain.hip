@@ -569,6 +569,16 @@ __device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int 
   }
 }
 
+// Lane l gets lane (l + M) mod 16 of its row of 16 (DPP row rotate).
+template <int M>
+__device__ __forceinline__ float dpp_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + M, 0xF, 0xF, false));
+}
+// Lane l gets lane l xor 16 (swizzle within groups of 32 lanes).
+__device__ __forceinline__ float swizzle_xor16(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+
 // Where the products hp_p[h] are read from: the hp buffer (hp[h * hs + p]),
 // or, with a single remaining mode (three-mode tensors), that mode's rows in
 // the row buffer directly.
@@ -694,8 +704,23 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
           }
         }
       }
-      if (colok) {
-        const int slot = (wp * hpt + hh) * Jn + jj;
+      // hpt a power of two with hpt J_n = 32: add the hpt lanes of each j_n
+      // (a fixed rotate-and-add order), one slot per wave part
+      const bool fold = hpt > 1 && (hpt & (hpt - 1)) == 0 && hpt * Jn == 32;
+      if (fold) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          float v = S[i];
+          if (Jn <= 1) v += dpp_ror<1>(v);
+          if (Jn <= 2) v += dpp_ror<2>(v);
+          if (Jn <= 4) v += dpp_ror<4>(v);
+          if (Jn <= 8) v += dpp_ror<8>(v);
+          v += swizzle_xor16(v);
+          S[i] = v;
+        }
+      }
+      if (fold ? hh == 0 : colok) {
+        const int slot = (fold ? wp : wp * hpt + hh) * Jn + jj;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -1629,7 +1654,9 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     t.ks2 = q.ks2;
     t.hpt = q.hpt;
     t.ctn = q.ctn;
-    t.ens = ts ? nwb * q.hpt : 1;
+    // (hpt a power of two filling the 32 columns: the contraction folds the hpt slots into one)
+    const bool fold = q.hpt > 1 && (q.hpt & (q.hpt - 1)) == 0 && q.hpt * s.J[n] == 32;
+    t.ens = ts ? (fold ? nwb : nwb * q.hpt) : 1;
   }
   for (int ph = N + 1; ph <= kMaxOrder; ++ph) a.pt[ph] = PhaseTab{};
 
