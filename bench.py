@@ -194,6 +194,7 @@ def run_c3(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dev = 0.0
+        chain_s = 0.0
         rmse = []
         done = 0
         for e in range(args.epochs):
@@ -205,14 +206,22 @@ def run_c3(args):
                 break
             done += 1
             dev += st["device_seconds"]
+            chain_s += st["chain_seconds"]
             rmse.append(round(h.loss(test_idx, test_vals)["rmse"], 6))
             log("c3 %s epoch %d: chain %.3fs held-out RMSE %.5f" % (dtype, e, st["chain_seconds"], rmse[-1]))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         info = h.info()
         h.close()
+        flops = (2 * len(wl.dims) + 4) * int(np.prod(wl.ranks))  # per nonzero-update
+        peak = 157.3 if dtype == "f32" else 2500.0
+        ach = wl.nnz * done * flops / chain_s / 1e12 if done else None
         res[dtype] = {"updates_per_s": round(wl.nnz * done / wall, 1) if done else None, "device_updates_per_s":
-                      round(wl.nnz * done / dev, 1) if done else None, "heldout_rmse_per_epoch": rmse,
+                      round(wl.nnz * done / dev, 1) if done else None,
+                      "roofline": {"bound": "mfma", "achieved": round(ach, 4) if done else None, "peak": peak,
+                                   "unit": "TFLOP/s", "frac": round(ach / peak, 6) if done else None, "traffic": None,
+                                   "kernel": "k_chain", "chain_seconds": round(chain_s, 4)},
+                      "heldout_rmse_per_epoch": rmse,
                       "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
                       "chain_chunk": info["chunk"]}
     oracle.build()
@@ -234,7 +243,7 @@ def run_c3(args):
                                   "uniform on 3-4), planted rank 8^4 + N(0,0.05^2), 10%% held out; J=(8,8,8,8), "
                                   "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
                       "train_entries": int(wl.nnz), "batch": M},
-           "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
+           "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
            "cpu_baseline": {"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1,
                             "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix}}
     print(json.dumps(out), flush=True)
