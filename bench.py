@@ -266,7 +266,7 @@ def cpu_baseline(h, wl, A0, G0, M, lr, lam, nbatches):
     from paper_2012_03550_amd import binding
     oracle.build()
     ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
-    log("oracle: running %d minibatches of epoch 0" % prefix)
+    log("oracle: running %d minibatches of epoch 0" % nbatches)
     t = time.perf_counter()
     ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3002, epoch0=0, n_epochs=1,
             max_batches=nbatches)
