@@ -243,71 +243,104 @@ __device__ __forceinline__ void write_row(float* buf, int ck, int chp, int p, in
 // adjacent words).  Fills the LDS table `split` (row, the run's first
 // boundary, then the new master row at +4) in row order.  If `store`, also
 // writes the rows (master, and BF16 copy in BF16 mode).
-template <int JR, bool EXACT, bool BF>
+template <int JR, bool EXACT, bool BF, bool GROUPED>
 __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
                                   const float* cbuf, float* split, int sstride, bool store) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = EXACT ? JR : a.s.J[pm];
   const int NS = 2 * a.W;
-  // entry -> its first boundary (kept in the entry's header word 1)
-  for (int bw = tid + 1; bw < a.W; bw += BT) {
-    const int e = xn[bw];
-    if (e >= 0) split[e * sstride + 1] = __int_as_float(bw);
-  }
-  __syncthreads();
-  // A group of GL lanes per entry (GL = 4, or fewer when there are more
-  // entries than the workgroup has quads): lane i sums the before-slots of
-  // boundaries bw + i, bw + i + GL, ... of the run (a long run of a popular
-  // row crosses many chunks), then the group adds up by a fixed butterfly
-  // (quad DPP) and its first lane adds the after-slot of the chunk where the
-  // run began.
-  const int GL = nsplit * 4 <= BT ? 4 : (nsplit * 2 <= BT ? 2 : 1);
-  const int g = tid / GL, i = tid % GL, ng = BT / GL;
-  for (int e0 = 0; e0 < nsplit; e0 += ng) {
-    const int e = e0 + g;
-    const bool ok = e < nsplit;
-    const int bw = ok ? __float_as_int(split[e * sstride + 1]) : 1;
-    const int row = ok ? xr[bw] : -2;
-    float F[JR];
-    int c = 0;
+  if (!GROUPED || a.W <= 32) {
+    // few boundaries, short runs: one thread per boundary where a run starts,
+    // summing the run's slots in chunk order
+    for (int bw = tid + 1; bw < a.W; bw += BT) {
+      const int e = xn[bw];
+      if (e < 0) continue;
+      const int row = xr[bw];
+      const float* slotB = cbuf + (bw - 1) * 2 + 1;
+      float F[JR];
+      int c = __float_as_int(slotB[NS]);
 #pragma unroll
-    for (int j = 0; j < JR; ++j) F[j] = 0.f;
-    for (int v = bw + i; ok && v < a.W && xr[v] == row; v += GL) {
-      const float* slotA = cbuf + v * 2;
-      c += __float_as_int(slotA[NS]);
-#pragma unroll
-      for (int j = 0; j < JR; ++j)
-        if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
-    }
-    if (GL >= 2) {  // lanes 2q, 2q+1 (and then the pairs of a quad): xor 1, then xor 2
-      c += __builtin_amdgcn_mov_dpp(c, 0xB1, 0xF, 0xF, false);
-#pragma unroll
-      for (int j = 0; j < JR; ++j)
-        if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0xB1, 0xF, 0xF, false));
-      if (GL == 4) {
-        c += __builtin_amdgcn_mov_dpp(c, 0x4E, 0xF, 0xF, false);
+      for (int j = 0; j < JR; ++j) F[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
+      for (int v = bw; v < a.W && xr[v] == row; ++v) {
+        const float* slotA = cbuf + v * 2;
+        c += __float_as_int(slotA[NS]);
 #pragma unroll
         for (int j = 0; j < JR; ++j)
-          if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0x4E, 0xF, 0xF, false));
+          if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
       }
-    }
-    if (ok && i == 0) {
-      const float* slotB = cbuf + (bw - 1) * 2 + 1;
       // (every LDS read before the first write: the compiler cannot tell the
       // table from the slots and would otherwise order each read after it)
-      float old[JR], Fb[JR];
-      const int cb = __float_as_int(slotB[NS]);
+      float old[JR];
 #pragma unroll
-      for (int j = 0; j < JR; ++j) {
-        Fb[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
-        old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
-      }
+      for (int j = 0; j < JR; ++j) old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
       float* ent = split + e * sstride;
       ent[0] = __int_as_float(row);
-      const float inv_c = 1.0f / (float)(c + cb);
+      const float inv_c = 1.0f / (float)c;
 #pragma unroll
       for (int j = 0; j < JR; ++j)
-        if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * ((Fb[j] + F[j]) * inv_c + a.lA * old[j]);
+        if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * (F[j] * inv_c + a.lA * old[j]);
+    }
+  } else {
+    // entry -> its first boundary (kept in the entry's header word 1)
+    for (int bw = tid + 1; bw < a.W; bw += BT) {
+      const int e = xn[bw];
+      if (e >= 0) split[e * sstride + 1] = __int_as_float(bw);
+    }
+    __syncthreads();
+    // A group of GL lanes per entry (GL = 4, or fewer when there are more
+    // entries than the workgroup has quads): lane i sums the before-slots of
+    // boundaries bw + i, bw + i + GL, ... of the run (a long run of a popular
+    // row crosses many chunks), then the group adds up by a fixed butterfly
+    // (quad DPP) and its first lane adds the after-slot of the chunk where the
+    // run began.
+    const int GL = nsplit * 4 <= BT ? 4 : (nsplit * 2 <= BT ? 2 : 1);
+    const int g = tid / GL, i = tid % GL, ng = BT / GL;
+    for (int e0 = 0; e0 < nsplit; e0 += ng) {
+      const int e = e0 + g;
+      const bool ok = e < nsplit;
+      const int bw = ok ? __float_as_int(split[e * sstride + 1]) : 1;
+      const int row = ok ? xr[bw] : -2;
+      float F[JR];
+      int c = 0;
+#pragma unroll
+      for (int j = 0; j < JR; ++j) F[j] = 0.f;
+      for (int v = bw + i; ok && v < a.W && xr[v] == row; v += GL) {
+        const float* slotA = cbuf + v * 2;
+        c += __float_as_int(slotA[NS]);
+#pragma unroll
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
+      }
+      if (GL >= 2) {  // lanes 2q, 2q+1 (and then the pairs of a quad): xor 1, then xor 2
+        c += __builtin_amdgcn_mov_dpp(c, 0xB1, 0xF, 0xF, false);
+#pragma unroll
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0xB1, 0xF, 0xF, false));
+        if (GL == 4) {
+          c += __builtin_amdgcn_mov_dpp(c, 0x4E, 0xF, 0xF, false);
+#pragma unroll
+          for (int j = 0; j < JR; ++j)
+            if (EXACT || j < pJ) F[j] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(F[j]), 0x4E, 0xF, 0xF, false));
+        }
+      }
+      if (ok && i == 0) {
+        const float* slotB = cbuf + (bw - 1) * 2 + 1;
+        // (every LDS read before the first write: the compiler cannot tell the
+        // table from the slots and would otherwise order each read after it)
+        float old[JR], Fb[JR];
+        const int cb = __float_as_int(slotB[NS]);
+#pragma unroll
+        for (int j = 0; j < JR; ++j) {
+          Fb[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
+          old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
+        }
+        float* ent = split + e * sstride;
+        ent[0] = __int_as_float(row);
+        const float inv_c = 1.0f / (float)(c + cb);
+#pragma unroll
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * ((Fb[j] + F[j]) * inv_c + a.lA * old[j]);
+      }
     }
   }
   __syncthreads();
@@ -1111,6 +1144,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   const int wv = tid >> 6;
   const int w = blockIdx.x;
   const ChainLayout& L = a.lay;
+  const bool CORE2 = NU != 3 && L.core2;  // two-level core update (never planned for three modes)
 
   float* Gs = lds + L.gs;
   float* TB = lds + L.tb;
@@ -1208,12 +1242,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           }
           if (tid == 0) xc = xsrc[2 * a.W];
         }
-        if (ph == 1 && !L.core2 && tid < P4) {
+        if (ph == 1 && !CORE2 && tid < P4) {
 #pragma unroll
           for (int v = 0; v < 8; ++v)
             if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
         }
-        if (ph == 1 && L.core2) {  // this thread's share of the workgroup's slice
+        if (ph == 1 && CORE2) {  // this thread's share of the workgroup's slice
           const int i = tid % L.cper, grp = tid / L.cper;
           const int l4 = min(w * L.cper + i, P4 - 1);
 #pragma unroll
@@ -1251,7 +1285,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       else nx.valid = false;
 
       // ---- 2. core: finish the core step of this minibatch
-      if (ph == 1 && L.core2) {
+      if (ph == 1 && CORE2) {
         // two levels: this workgroup's slice of G, one grid barrier, then all of G
         f32x4* red = reinterpret_cast<f32x4*>(lds + L.red);
         const int i = tid % L.cper, grp = tid / L.cper;
@@ -1323,7 +1357,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
         const int nsplit = misc[0];
-        finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
+        finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
         // the schedule says which entry (if any) holds this sample's mode-pm row
         const int pe = (cur.meta >> kMetaPatchShift) & 0xFF;
         if (active && pe > 0) {
@@ -1506,7 +1540,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     if (tid == 0) misc[0] = xsrc[2 * a.W];
     copy_carry(a, ppar, cbuf);
     __syncthreads();
-    finish_split_rows<JR, EXACT, BF>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true);
+    finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true);
   }
   if (w == 0)
     for (int lin = tid; lin < P; lin += BT) a.G[lin] = Gs[lin];
@@ -1592,7 +1626,8 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     const int per = (P4 + a.W - 1) / a.W;
     const int grp = per <= threads ? threads / per : 0;
     const int vg = grp > 0 ? (a.W + grp - 1) / grp : 0;
-    L.core2 = (a.W >= 8 && grp >= 1 && vg <= 8 && (long long)P4 * a.W >= 8192) ? 1 : 0;
+    // (three-mode kernels always take the one-level update)
+    L.core2 = (N != 3 && a.W >= 8 && grp >= 1 && vg <= 8 && (long long)P4 * a.W >= 8192) ? 1 : 0;
     L.cper = per;
     L.cgrp = grp;
     L.cvg = vg;
