@@ -1390,6 +1390,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       if constexpr (HPV) {
         hpr = HpRef<HPV, BF>{rowbuf, chp, pt.c_hi};
       } else {
+        // (build_hp2 reads other threads' samples: the patched rows must have landed)
+        if (splits && EXACT && pt.nhi == 2) __syncthreads();
         if (EXACT && pt.nhi == 2) build_hp2<JR, BF>(pt, rowbuf, cnt, chp, hp, L.hs);
         else build_hp<BF>(pt, rowbuf, hmap + pt.hm_off, cnt, chp, hp, L.hs);
         hpr = HpRef<HPV, BF>{hp, L.hs, 0};

@@ -306,3 +306,38 @@ def test_bf16_planted_rmse_gap(lib, oracle_mod):
     wl = synth.planted_uniform(seed=1001)
     compare_epochs(lib, oracle_mod, "c1_bf16", wl.dims, wl.ranks, wl.train_idx, wl.train_vals, 256, epochs=10,
                    lr=0.01, lam=0.01, test=(wl.test_idx, wl.test_vals), dtype="bf16", tol=BF16_TOL, rmse_tol=1e-2)
+
+
+# ------------------------------------------- every row after a few minibatches
+# Row-level check after one and two minibatches, in one launch and in one
+# launch per minibatch: the largest absolute error of any parameter against
+# the oracle.  Rows that straddle chunk boundaries are finished by the next
+# sub-step (or at the end of a launch) and patched into other workgroups'
+# samples; an error there touches a handful of rows, which the per-epoch
+# relative norms above can miss.  FP32 rounding of O(1) parameters after a
+# few steps stays far below the bound.
+ROW_TOL = 1e-6
+ROW_CASES = [((200, 150, 100), (4, 4, 4), 32), ((200, 150, 100), (4, 4, 4), 64), ((200, 150, 100), (4, 4, 4), 128),
+             ((60, 50, 30, 20), (8, 8, 8, 8), 64), ((60, 50, 30, 20), (8, 8, 8, 8), 128)]
+
+
+@pytest.mark.parametrize("dims,ranks,chunk", ROW_CASES, ids=["n%d_j%d_chunk%d" % (len(c[0]), c[1][0], c[2]) for c in ROW_CASES])
+def test_rows_after_minibatches(lib, oracle_mod, dims, ranks, chunk):
+    idx, vals = synth.random_tiny(len(dims), dims, ranks, 20000, seed=9, skew=1.2)
+    A0, G0 = synth.init_params(dims, ranks, seed=9)
+    say("rows", dims, ranks, "chunk", chunk)
+    for nb in (1, 2):
+        ref = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+        ref.run(idx, vals, 512, 0.01, 0.01, 0.01, 0.01, seed=77, epoch0=0, n_epochs=1, max_batches=nb)
+        for split in (False, True):
+            h = make_handle(lib, dims, ranks, idx, vals, A0, G0, 512, seed=77, chunk=chunk)
+            if split:
+                for k in range(nb):
+                    h.run_minibatches(0, k, k + 1)
+            else:
+                h.run_minibatches(0, 0, nb)
+            A, G = h.get_params()
+            h.close()
+            errs = [float(np.max(np.abs(a - r))) for a, r in zip(A, ref.A)] + [float(np.max(np.abs(G - ref.G)))]
+            say("  minibatches", nb, "split launches" if split else "one launch", "max abs errors", errs)
+            assert max(errs) <= ROW_TOL, errs
