@@ -49,9 +49,8 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRowTail = 32;
 
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (unsigned short)((u >> 16) | 0x40u);
-  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  // round to nearest even (gfx950 converts in hardware, NaN stays NaN)
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float((uint32_t)bf16_bits(f) << 16); }
 __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
@@ -978,18 +977,30 @@ __device__ __forceinline__ void mfma_core_grad(const Shape& s, const PhaseTab& g
         }
       }
     } else {
-      for (int st = 0; st < nsteps; ++st) {  // no masks (see the FP32 path); 16 * nsteps <= chp
+      // no masks (see the FP32 path); 16 * nsteps <= chp.  The operands of
+      // step st + 1 are read before the MFMAs of step st; with one row tile
+      // both output tiles share the A operand.
+      const bool oneA = MT0 == 1;
+      struct Ops {
         s16x4 aa, ab, ba, bb;
+      };
+      auto load = [&](int st, Ops& o) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int p = st * 16 + 4 * kq + e;
-          aa[e] = (short)bf16_bits(ra[p * ras + j0a]);
-          ab[e] = (short)bf16_bits(ra[p * ras + j0b]);
-          ba[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jla) * hpr.one(p, ha));
-          bb[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jlb) * hpr.one(p, hb));
+          o.aa[e] = (short)bf16_bits(ra[p * ras + j0a]);
+          o.ab[e] = oneA ? o.aa[e] : (short)bf16_bits(ra[p * ras + j0b]);
+          o.ba[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jla) * hpr.one(p, ha));
+          o.bb[e] = (short)bf16_bits(row_at<BF>(rowbuf, clo, chp, p, jlb) * hpr.one(p, hb));
         }
-        acca = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aa, ba, acca, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab, bb, accb, 0, 0, 0);
+      };
+      Ops cur, nxt;
+      if (nsteps > 0) load(0, cur);
+      for (int st = 0; st < nsteps; ++st) {
+        load(st + 1 < nsteps ? st + 1 : st, nxt);
+        acca = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur.aa, cur.ba, acca, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur.ab, cur.bb, accb, 0, 0, 0);
+        cur = nxt;
       }
     }
 #pragma unroll
