@@ -232,6 +232,50 @@ __device__ __forceinline__ void write_row(float* buf, int ck, int chp, int p, in
   }
 }
 
+// Segmented inclusive sum over the 64 lanes of a wave (fixed order): lane l
+// adds the values of lanes [ws, l), ws = the first lane of its segment
+// (ws <= l).  Within each row of 16 lanes by DPP row shifts (1, 2, 4, 8),
+// then across rows by the row broadcasts of lanes 15 and 31.
+template <int D>
+__device__ __forceinline__ float dpp_row_shr(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_bcast15(float v) {  // rows 1 and 3 get lanes 15 and 47, rows 0 and 2 get 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+}
+__device__ __forceinline__ float dpp_bcast31(float v) {  // rows 2 and 3 get lane 31, rows 0 and 1 get 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+}
+
+template <int JR, bool EXACT>
+__device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int lane, int ws) {
+  const int rl = lane & 15;
+  const bool t1 = rl >= 1 && lane - 1 >= ws, t2 = rl >= 2 && lane - 2 >= ws;
+  const bool t4 = rl >= 4 && lane - 4 >= ws, t8 = rl >= 8 && lane - 8 >= ws;
+  const int row = lane >> 4;
+  const bool t15 = (row & 1) && (lane | 15) - 16 >= ws;  // lane 16*row - 1
+  const bool t31 = row >= 2 && 31 >= ws;
+#pragma unroll
+  for (int j = 0; j < JR; ++j) {
+    if (EXACT || j < Jn) {
+      float v = u[j];
+      float o = dpp_row_shr<1>(v);
+      v += t1 ? o : 0.f;
+      o = dpp_row_shr<2>(v);
+      v += t2 ? o : 0.f;
+      o = dpp_row_shr<4>(v);
+      v += t4 ? o : 0.f;
+      o = dpp_row_shr<8>(v);
+      v += t8 ? o : 0.f;
+      o = dpp_bcast15(v);
+      v += t15 ? o : 0.f;
+      o = dpp_bcast31(v);
+      v += t31 ? o : 0.f;
+      u[j] = v;
+    }
+  }
+}
+
 // Finish the rows that straddled chunk boundaries in the previous factor
 // sub-step (mode pm).  xr[bw] is the straddling row at boundary bw or -1,
 // xn[bw] the entry number of a row's first boundary or -1 (both from the
@@ -248,9 +292,52 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = EXACT ? JR : a.s.J[pm];
   const int NS = 2 * a.W;
-  if (!GROUPED || a.W <= 32) {
-    // few boundaries, short runs: one thread per boundary where a run starts,
-    // summing the run's slots in chunk order
+  if (a.W <= 64) {
+    // all boundaries in one wave: lane v loads the before-slot of chunk v,
+    // a segmented scan over the runs of equal rows adds them in a fixed
+    // tree order, and the run's last lane adds the after-slot of the chunk
+    // where the run began and writes the entry
+    if (tid < 64) {
+      const int v = tid;
+      const int rowv = (v >= 1 && v < a.W) ? xr[v] : -1;
+      const int rowp = (v >= 2 && v - 1 < a.W) ? xr[v - 1] : -1;
+      const int rown = (v + 1 < a.W) ? xr[v + 1] : -1;
+      const bool live = rowv >= 0;
+      const bool first = live && rowp != rowv;
+      const bool last = live && rown != rowv;
+      const unsigned long long starts = __ballot(first);
+      const unsigned long long upto = v == 63 ? ~0ull : ((2ull << v) - 1);
+      const int ws = live ? 63 - __clzll(starts & upto) : v;  // first boundary of my run
+      const float* slotA = cbuf + min(v, a.W - 1) * 2;
+      float u[JR], cc[1];
+      cc[0] = live ? (float)__float_as_int(slotA[NS]) : 0.f;
+#pragma unroll
+      for (int j = 0; j < JR; ++j) u[j] = (live && (EXACT || j < pJ)) ? slotA[(2 + j) * NS] : 0.f;
+      wave_segmented_scan<JR, EXACT>(u, pJ, v, ws);
+      wave_segmented_scan<1, true>(cc, 1, v, ws);
+      if (last) {
+        const int e = xn[ws];
+        const float* slotB = cbuf + (ws - 1) * 2 + 1;
+        // (every LDS read before the first write: the compiler cannot tell the
+        // table from the slots and would otherwise order each read after it)
+        float old[JR], Fb[JR];
+        const int c = (int)cc[0] + __float_as_int(slotB[NS]);
+#pragma unroll
+        for (int j = 0; j < JR; ++j) {
+          Fb[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
+          old[j] = (EXACT || j < pJ) ? slotB[(2 + pJ + j) * NS] : 0.f;
+        }
+        float* ent = split + e * sstride;
+        ent[0] = __int_as_float(rowv);
+        const float inv_c = 1.0f / (float)c;
+#pragma unroll
+        for (int j = 0; j < JR; ++j)
+          if (EXACT || j < pJ) ent[4 + j] = old[j] - a.gA * ((Fb[j] + u[j]) * inv_c + a.lA * old[j]);
+      }
+    }
+  } else if (!GROUPED) {
+    // one thread per boundary where a run starts, summing the run's slots in
+    // chunk order
     for (int bw = tid + 1; bw < a.W; bw += BT) {
       const int e = xn[bw];
       if (e < 0) continue;
@@ -554,50 +641,6 @@ __device__ __forceinline__ void build_hp2(const PhaseTab& pt, const float* rowbu
       if (j == d2) v2 = r2[j];
 #pragma unroll
     for (int d1 = 0; d1 < JR; ++d1) hp[(d1 + JR * d2) * hs + p] = r1[d1] * v2;
-  }
-}
-
-// Segmented inclusive sum over the 64 lanes of a wave (fixed order): lane l
-// adds the values of lanes [ws, l), ws = the first lane of its segment
-// (ws <= l).  Within each row of 16 lanes by DPP row shifts (1, 2, 4, 8),
-// then across rows by the row broadcasts of lanes 15 and 31.
-template <int D>
-__device__ __forceinline__ float dpp_row_shr(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float dpp_bcast15(float v) {  // rows 1 and 3 get lanes 15 and 47, rows 0 and 2 get 0
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
-}
-__device__ __forceinline__ float dpp_bcast31(float v) {  // rows 2 and 3 get lane 31, rows 0 and 1 get 0
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
-}
-
-template <int JR, bool EXACT>
-__device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int lane, int ws) {
-  const int rl = lane & 15;
-  const bool t1 = rl >= 1 && lane - 1 >= ws, t2 = rl >= 2 && lane - 2 >= ws;
-  const bool t4 = rl >= 4 && lane - 4 >= ws, t8 = rl >= 8 && lane - 8 >= ws;
-  const int row = lane >> 4;
-  const bool t15 = (row & 1) && (lane | 15) - 16 >= ws;  // lane 16*row - 1
-  const bool t31 = row >= 2 && 31 >= ws;
-#pragma unroll
-  for (int j = 0; j < JR; ++j) {
-    if (EXACT || j < Jn) {
-      float v = u[j];
-      float o = dpp_row_shr<1>(v);
-      v += t1 ? o : 0.f;
-      o = dpp_row_shr<2>(v);
-      v += t2 ? o : 0.f;
-      o = dpp_row_shr<4>(v);
-      v += t4 ? o : 0.f;
-      o = dpp_row_shr<8>(v);
-      v += t8 ? o : 0.f;
-      o = dpp_bcast15(v);
-      v += t15 ? o : 0.f;
-      o = dpp_bcast31(v);
-      v += t31 ? o : 0.f;
-      u[j] = v;
-    }
   }
 }
 
