@@ -244,9 +244,23 @@ def run_c3(args):
                                   "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
                       "train_entries": int(wl.nnz), "batch": M},
            "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
-           "cpu_baseline": {"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1,
-                            "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix}}
+           "cpu_baseline": dict({"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1,
+                                 "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix},
+                                **host_cpu())}
     print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    """The host's CPU model and hardware thread count (where the oracle baseline ran)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"host_cpu": model, "host_threads": os.cpu_count()}
 
 
 def kernel_source_hash():
@@ -280,10 +294,10 @@ def cpu_baseline(h, wl, A0, G0, M, lr, lam, nbatches):
     err = max([float(np.linalg.norm(Ag[n] - ref.A[n]) / np.linalg.norm(ref.A[n])) for n in range(3)] +
               [float(np.linalg.norm(Gg - ref.G) / np.linalg.norm(ref.G))])
     log("cpu oracle: %d minibatches in %.2fs; GPU vs oracle on that prefix: max rel err %.3g" % (nbatches, dt, err))
-    return {"value": round(nbatches * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d minibatches (%d updates) of epoch 0 from the same initial parameters, FP64 C, "
-                      "one thread" % (nbatches, nbatches * M),
-            "gpu_prefix_max_rel_err": err}
+    return dict({"value": round(nbatches * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
+                 "sample": "first %d minibatches (%d updates) of epoch 0 from the same initial parameters, FP64 C, "
+                           "one thread" % (nbatches, nbatches * M),
+                 "gpu_prefix_max_rel_err": err}, **host_cpu())
 
 
 if __name__ == "__main__":
