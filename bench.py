@@ -52,10 +52,16 @@ def main():
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
         for _ in range(5):
             dst.copy_(src)
+        ev[1].record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 5}))
+        sec = ev[0].elapsed_time(ev[1]) * 1e-3 / 5
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 6,
+                          "copy_GBs_read_plus_write": round(2 * n * 4 / sec / 1e9, 1)}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -123,7 +129,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 6), "traffic": traffic,
                 "kernel": "k_chain", "avg_launch_ms": round(avg_launch * 1e3, 3),
-                "hbm_alg_GBs": round(acc["bytes_alg"] / acc["chain_seconds"] / 1e9, 2)}
+                "hbm_alg_GBs": round(acc["bytes_alg"] / acc["chain_seconds"] / 1e9, 2),
+                "latency_bound": latency_bound(h, M, len(wl.dims), updates / acc["chain_seconds"])}
 
     cpu = None
     if args.cpu_batches > 0:
@@ -212,6 +219,7 @@ def run_c3(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         info = h.info()
+        lat = latency_bound(h, M, len(wl.dims), wl.nnz * done / chain_s) if done else None
         h.close()
         flops = (2 * len(wl.dims) + 4) * int(np.prod(wl.ranks))  # per nonzero-update
         peak = 157.3 if dtype == "f32" else 2500.0
@@ -220,7 +228,7 @@ def run_c3(args):
                       round(wl.nnz * done / dev, 1) if done else None,
                       "roofline": {"bound": "mfma", "achieved": round(ach, 4) if done else None, "peak": peak,
                                    "unit": "TFLOP/s", "frac": round(ach / peak, 6) if done else None, "traffic": None,
-                                   "kernel": "k_chain", "chain_seconds": round(chain_s, 4)},
+                                   "kernel": "k_chain", "chain_seconds": round(chain_s, 4), "latency_bound": lat},
                       "heldout_rmse_per_epoch": rmse,
                       "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
                       "chain_chunk": info["chunk"]}
@@ -248,6 +256,15 @@ def run_c3(args):
                                  "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix},
                                 **host_cpu())}
     print(json.dumps(out), flush=True)
+
+
+def latency_bound(h, M, N, chain_rate):
+    """The chain's grid barrier timed alone: a minibatch is N + 1 dependent
+    sub-steps, so no chain exceeds M / ((N + 1) t_sync) updates/s."""
+    t = h.barrier_us(2000)
+    bound = M / ((N + 1) * t * 1e-6)
+    return {"t_sync_us": round(t, 3), "sub_steps": N + 1, "updates_per_s": round(bound, 1),
+            "chain_frac": round(chain_rate / bound, 4)}
 
 
 def host_cpu():

@@ -161,6 +161,14 @@ int stdecomp_set_epoch(stdecomp_handle* h, int64_t e);
 int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, int32_t mode, int64_t* entries,
                             int32_t* sigma, int32_t* seg_off, int32_t* seg_row, int32_t* nseg, int32_t* m_out);
 
+/* Measurement aid: the chain's grid barrier alone (the handle's W workgroups,
+ * `reps` barriers in a row, 1 <= reps <= 1000000), timed with events on the
+ * handle's stream; *us_per_barrier receives the mean time of one barrier in
+ * microseconds.  With N + 1 dependent sub-steps per minibatch of m entries a
+ * chain cannot exceed m / ((N + 1) t_sync) updates/s.  STD_E_INVAL for a bad
+ * reps or a null output, STD_E_DEVICE if a workgroup gave up waiting. */
+int stdecomp_debug_barrier(stdecomp_handle* h, int32_t reps, double* us_per_barrier);
+
 /* The GPU sampler alone: out[q] = pi_e(q) for q in [0, T), host output. */
 int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out);
 

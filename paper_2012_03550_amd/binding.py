@@ -70,6 +70,7 @@ SIGNATURES = {
                                                _i32p, _i32p, _i32p, _i32p, _i32p]),
     "stdecomp_sample_order": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, _i64p]),
     "stdecomp_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(InfoOut)]),
+    "stdecomp_debug_barrier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "stdecomp_free": (ctypes.c_int, [ctypes.c_void_p]),
     "stdecomp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stdecomp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -256,6 +257,12 @@ class Stdecomp:
             m.ctypes.data_as(_i32p)), "stdecomp_debug_schedule")
         mm, d = int(m[0]), int(nseg[0])
         return dict(entries=entries[:mm], sigma=sigma[:mm], seg_off=seg_off[: d + 1], seg_row=seg_row[:d])
+
+    def barrier_us(self, reps=2000):
+        """Mean time of the chain's grid barrier alone, in microseconds."""
+        us = ctypes.c_double(0.0)
+        self._check(load().stdecomp_debug_barrier(self._h, reps, ctypes.byref(us)), "stdecomp_debug_barrier")
+        return us.value
 
     def info(self):
         out = InfoOut()

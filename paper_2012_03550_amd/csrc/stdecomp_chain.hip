@@ -1602,6 +1602,24 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     for (int lin = tid; lin < P; lin += BT) a.G[lin] = Gs[lin];
 }
 
+// The chain's grid barrier alone, `reps` times in a row (no other work): the
+// sync cost t_sync that bounds a chain at m / ((N + 1) t_sync) updates/s.
+__global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, int reps) {
+  __shared__ int flag[1];
+  unsigned passed = 0;
+  for (int r = 0; r < reps; ++r) {
+    passed += 1;
+    barrier_arrive(a, passed);
+    if (!barrier_wait(a, passed, flag)) return;
+  }
+}
+
+hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st) {
+  ChainArgs args = a;
+  void* params[] = {&args, &reps};
+  return hipLaunchCooperativeKernel((const void*)k_barrier_probe, dim3(a.W), dim3(threads), params, 0, st);
+}
+
 // ---------------------------------------------------------------------------
 // Host side: the LDS plan, the per-phase constants and the index maps.
 // ---------------------------------------------------------------------------

@@ -142,6 +142,7 @@ hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const
 size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
 size_t chain_lds_bytes(const ChainArgs& a, int threads);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
+hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
                                uint32_t* rec, int* bad, hipStream_t st);
 struct FactorPtrs {

@@ -768,6 +768,26 @@ int stdecomp_set_epoch(stdecomp_handle* h, int64_t e) {
   return STD_OK;
 }
 
+int stdecomp_debug_barrier(stdecomp_handle* h, int32_t reps, double* us_per_barrier) {
+  if (!h) return STD_E_STATE;
+  if (reps < 1 || reps > 1000000 || !us_per_barrier) return fail(h, STD_E_INVAL, "bad barrier probe arguments");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, STD_E_DEVICE, "hipSetDevice failed");
+  stdk::ChainArgs a = chain_args(h);
+  HIPCHK(h, hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+  HIPCHK(h, hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h->stream));
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream));
+  HIPCHK(h, stdk::launch_barrier_probe(a, h->threads, reps, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
+  int err = 0;
+  HIPCHK(h, hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (err) return fail(h, STD_E_DEVICE, "barrier probe: a workgroup gave up waiting");
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  *us_per_barrier = 1000.0 * ms / reps;
+  return STD_OK;
+}
+
 int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, int32_t mode, int64_t* entries,
                             int32_t* sigma, int32_t* seg_off, int32_t* seg_row, int32_t* nseg, int32_t* m_out) {
   if (!h) return STD_E_STATE;
