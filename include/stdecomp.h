@@ -161,6 +161,19 @@ int stdecomp_set_epoch(stdecomp_handle* h, int64_t e);
 int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, int32_t mode, int64_t* entries,
                             int32_t* sigma, int32_t* seg_off, int32_t* seg_row, int32_t* nseg, int32_t* m_out);
 
+/* n_epochs epochs of each of n independent models, as stdecomp_epoch on each
+ * (Algorithm 1 on every tensor; results identical to running the handles
+ * alone), with all of their minibatch chains in one cooperative launch when
+ * they share a kernel (equal ranks 4, 8 or 16 in every mode, the same class
+ * of order, three or other, the same dtype and device), the handles are
+ * distinct, and their workgroups fit the device at once; otherwise the
+ * handles run one after another.  hs: n >= 1 handles (caller-owned); st:
+ * NULL or n caller-owned records, where chain_seconds and device_seconds are
+ * the time of the whole batched launch.  Allocates two small device buffers
+ * per call.  STD_E_INVAL for n < 1 or a null array, STD_E_STATE for a null
+ * handle; otherwise as stdecomp_epoch (reported on hs[0]). */
+int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st);
+
 /* Measurement aid: the chain's grid barrier alone (the handle's W workgroups,
  * `reps` barriers in a row, 1 <= reps <= 1000000), timed with events on the
  * handle's stream; *us_per_barrier receives the mean time of one barrier in

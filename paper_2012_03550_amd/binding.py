@@ -71,6 +71,8 @@ SIGNATURES = {
     "stdecomp_sample_order": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, _i64p]),
     "stdecomp_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(InfoOut)]),
     "stdecomp_debug_barrier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "stdecomp_epoch_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(EpochStats)]),
     "stdecomp_free": (ctypes.c_int, [ctypes.c_void_p]),
     "stdecomp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stdecomp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -268,6 +270,18 @@ class Stdecomp:
         out = InfoOut()
         self._check(load().stdecomp_info(self._h, ctypes.byref(out)), "stdecomp_info")
         return {f: getattr(out, f) for f, _ in InfoOut._fields_}
+
+
+def epoch_batched(handles, n_epochs=1):
+    """n_epochs epochs of every model in `handles` (Stdecomp objects), their
+    chains in one launch where they share a kernel."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h._h.value for h in handles])
+    st = (EpochStats * n)()
+    rc = load().stdecomp_epoch_batched(arr, n, n_epochs, st)
+    if rc != 0:
+        handles[0]._check(rc, "stdecomp_epoch_batched")
+    return [{f: getattr(s, f) for f, _ in EpochStats._fields_} for s in st]
 
 
 def sample_order(T, seed, epoch):

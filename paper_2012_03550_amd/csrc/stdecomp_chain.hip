@@ -73,11 +73,11 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 // counter 0 (bits 3:0 and 15:14), export and LDS/scalar counters at their maxima.
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-__device__ __forceinline__ void barrier_arrive(const ChainArgs& a, unsigned passed) {
+__device__ __forceinline__ void barrier_arrive(const ChainArgs& a, int w, unsigned passed) {
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (threadIdx.x == 0)
-    __hip_atomic_store(a.bar + blockIdx.x * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.bar + w * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed, int* flag_lds) {
@@ -123,11 +123,11 @@ struct LaneRec {
 };
 
 template <int NM>
-__device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int N, int64_t b, int ph, LaneRec<NM>& r) {
+__device__ __forceinline__ void load_lane_rec(const ChainArgs& a, int w, int N, int64_t b, int ph, LaneRec<NM>& r) {
   const PhaseTab& pt = a.pt[ph];
   const int64_t base = b * a.M;
   const int m = (int)((a.T - base < a.M) ? (a.T - base) : a.M);
-  const int q = blockIdx.x * a.chunk + (int)threadIdx.x;
+  const int q = w * a.chunk + (int)threadIdx.x;
   r.valid = (int)threadIdx.x < a.chunk && q < m;
 #pragma unroll
   for (int k = 0; k < NM; ++k) r.idx[k] = 0;
@@ -1181,7 +1181,7 @@ __device__ __forceinline__ void copy_carry(const ChainArgs& a, int par, float* c
 // old row; stored element-major (element e of slot sl at e * 2W + sl).
 // ---------------------------------------------------------------------------
 template <int JU, int NU, int BFI>
-__global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
+__device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
   constexpr int JR = JU ? JU : kMaxRank;
   constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
@@ -1196,7 +1196,6 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   const int BT = blockDim.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int w = blockIdx.x;
   const ChainLayout& L = a.lay;
   const bool CORE2 = NU != 3 && L.core2;  // two-level core update (never planned for three modes)
 
@@ -1249,7 +1248,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   bool first = true;
 
   LaneRec<NM> cur;
-  if (a.b_begin < a.b_end) load_lane_rec<NM>(a, N, a.b_begin, 0, cur);
+  if (a.b_begin < a.b_end) load_lane_rec<NM>(a, w, N, a.b_begin, 0, cur);
   else cur.valid = false;
   int bsel = 0;  // which row buffer holds the current sub-step's rows
   float an_cur[JR], an_nxt[JR];  // BF16 mode: FP32 master row of the lane's own-mode row
@@ -1335,7 +1334,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       }
       const bool has_next = nbb < a.b_end;
       LaneRec<NM> nx;
-      if (has_next) load_lane_rec<NM>(a, N, nbb, nph, nx);
+      if (has_next) load_lane_rec<NM>(a, w, N, nbb, nph, nx);
       else nx.valid = false;
 
       // ---- 2. core: finish the core step of this minibatch
@@ -1363,7 +1362,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
           }
         }
         passed += 1;
-        barrier_arrive(a, passed);
+        barrier_arrive(a, w, passed);
         if (!barrier_wait(a, passed, misc + 7)) return;
         for (int l4b = tid; l4b < P4; l4b += BT) {
           float gv[4];
@@ -1566,7 +1565,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
       //      the resident tables the core update changed, or, with one table
       //      region, the next phase's table.
       passed += 1;
-      barrier_arrive(a, passed);
+      barrier_arrive(a, w, passed);
       if (ph == 1 && L.tb_all) {
         for (int n2 = 1; n2 < N; ++n2) {
           const PhaseTab& q = a.pt[n2 + 1];
@@ -1602,6 +1601,22 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
     for (int lin = tid; lin < P; lin += BT) a.G[lin] = Gs[lin];
 }
 
+template <int JU, int NU, int BFI>
+__global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
+  chain_body<JU, NU, BFI>(a, blockIdx.x);
+}
+
+// Several independent chains in one cooperative launch (one per tensor of a
+// batch): workgroup g runs workgroup map[g].y of chain map[g].x, whose
+// arguments (own buffers, barrier flags and minibatch range) are all[map[g].x].
+// A chain with an empty range exits at once; the others never wait for it.
+template <int JU, int NU, int BFI>
+__global__ __launch_bounds__(kChainThreads) void k_chain_multi(const ChainArgs* __restrict__ all,
+                                                               const int2* __restrict__ map) {
+  const int2 m = map[blockIdx.x];
+  chain_body<JU, NU, BFI>(all[m.x], m.y);
+}
+
 // The chain's grid barrier alone, `reps` times in a row (no other work): the
 // sync cost t_sync that bounds a chain at m / ((N + 1) t_sync) updates/s.
 __global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, int reps) {
@@ -1609,7 +1624,7 @@ __global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, in
   unsigned passed = 0;
   for (int r = 0; r < reps; ++r) {
     passed += 1;
-    barrier_arrive(a, passed);
+    barrier_arrive(a, blockIdx.x, passed);
     if (!barrier_wait(a, passed, flag)) return;
   }
 }
@@ -1845,6 +1860,44 @@ hipError_t launch_chain_n(const ChainArgs& a, int threads, size_t bytes, hipStre
   const bool n3 = a.s.N == 3;
   if (bf) return n3 ? launch_chain_t<JU, 3, 1>(a, threads, bytes, st) : launch_chain_t<JU, 0, 1>(a, threads, bytes, st);
   return n3 ? launch_chain_t<JU, 3, 0>(a, threads, bytes, st) : launch_chain_t<JU, 0, 0>(a, threads, bytes, st);
+}
+
+template <int JU, int NU, int BFI>
+hipError_t launch_multi_t(const ChainArgs* dev_args, const int* dev_map, int wgs, int threads, size_t bytes,
+                          hipStream_t st) {
+  const ChainArgs* pa = dev_args;
+  const int2* pm = reinterpret_cast<const int2*>(dev_map);
+  void* params[] = {&pa, &pm};
+  hipError_t e = hipFuncSetAttribute((const void*)k_chain_multi<JU, NU, BFI>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipLaunchCooperativeKernel((const void*)k_chain_multi<JU, NU, BFI>, dim3(wgs), dim3(threads), params,
+                                   (unsigned)bytes, st);
+  return e;
+}
+
+template <int JU>
+hipError_t launch_multi_j(int n3, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs, int threads,
+                          size_t bytes, hipStream_t st) {
+  if (bf) return n3 ? launch_multi_t<JU, 3, 1>(dev_args, dev_map, wgs, threads, bytes, st)
+                    : launch_multi_t<JU, 0, 1>(dev_args, dev_map, wgs, threads, bytes, st);
+  return n3 ? launch_multi_t<JU, 3, 0>(dev_args, dev_map, wgs, threads, bytes, st)
+            : launch_multi_t<JU, 0, 0>(dev_args, dev_map, wgs, threads, bytes, st);
+}
+
+bool chain_multi_supported(const Shape& s) {
+  const int v = chain_variant(s);
+  return v == 4 || v == 8 || v == 16;
+}
+
+hipError_t launch_chain_multi(const Shape& s, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs,
+                              int threads, size_t bytes, hipStream_t st) {
+  const int v = chain_variant(s);
+  const int n3 = s.N == 3;
+  if (v == 4) return launch_multi_j<4>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
+  if (v == 8) return launch_multi_j<8>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
+  if (v == 16) return launch_multi_j<16>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {

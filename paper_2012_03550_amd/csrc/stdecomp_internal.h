@@ -143,6 +143,13 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
 size_t chain_lds_bytes(const ChainArgs& a, int threads);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st);
+// Several chains of one kernel variant (equal rank 4, 8 or 16; the same order
+// class and dtype) in one cooperative launch: dev_args[t] are chain t's
+// arguments, dev_map[2 g], dev_map[2 g + 1] = (chain, workgroup) of grid
+// workgroup g; bytes = the largest LDS plan among them.
+bool chain_multi_supported(const Shape& s);
+hipError_t launch_chain_multi(const Shape& s, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs,
+                              int threads, size_t bytes, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
                                uint32_t* rec, int* bad, hipStream_t st);
 struct FactorPtrs {

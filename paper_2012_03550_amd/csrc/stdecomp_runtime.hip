@@ -656,6 +656,113 @@ int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* s
   return check_finite(h);
 }
 
+int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st) {
+  if (!hs || n < 1) return STD_E_INVAL;
+  for (int i = 0; i < n; ++i)
+    if (!hs[i]) return STD_E_STATE;
+  stdecomp_handle* h0 = hs[0];
+  if (n_epochs < 0) return fail(h0, STD_E_INVAL, "n_epochs < 0");
+  // one launch needs the same kernel variant, device and dtype, distinct
+  // handles, and room for every chain's workgroups at once
+  bool one_launch = stdk::chain_multi_supported(h0->s);
+  int total_w = 0;
+  size_t lds = 0;
+  for (int i = 0; i < n && one_launch; ++i) {
+    const stdecomp_handle* h = hs[i];
+    one_launch = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads &&
+                 stdk::chain_variant(h->s) == stdk::chain_variant(h0->s) && (h->s.N == 3) == (h0->s.N == 3);
+    for (int k = 0; k < i && one_launch; ++k) one_launch = hs[k] != h;
+    total_w += h->W;
+    lds = h->chain_lds > lds ? h->chain_lds : lds;
+  }
+  if (one_launch && total_w > h0->num_cus) one_launch = false;
+  if (!one_launch) {  // the same updates, one handle after another
+    for (int i = 0; i < n; ++i) {
+      int rc = stdecomp_epoch(hs[i], n_epochs, st ? &st[i] : nullptr);
+      if (rc) return rc;
+    }
+    return STD_OK;
+  }
+  if (hipSetDevice(h0->device) != hipSuccess) return fail(h0, STD_E_DEVICE, "hipSetDevice failed");
+  std::vector<int> map((size_t)2 * total_w);
+  int64_t max_nb = 0;
+  for (int i = 0, g = 0; i < n; ++i) {
+    for (int w = 0; w < hs[i]->W; ++w, ++g) {
+      map[2 * g] = i;
+      map[2 * g + 1] = w;
+    }
+    max_nb = hs[i]->nb > max_nb ? hs[i]->nb : max_nb;
+  }
+  stdk::ChainArgs* dargs = nullptr;
+  int* dmap = nullptr;
+  if (hipMalloc((void**)&dargs, sizeof(stdk::ChainArgs) * n) != hipSuccess ||
+      hipMalloc((void**)&dmap, sizeof(int) * map.size()) != hipSuccess) {
+    hipFree(dargs);
+    return fail(h0, STD_E_NOMEM, "batched launch: device allocation failed");
+  }
+  std::vector<stdk::ChainArgs> args((size_t)n);
+  std::vector<stdecomp_epoch_stats> acc((size_t)n);
+  int rc = STD_OK;
+  auto hipck = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipSuccess;
+  };
+  if (hipck(hipMemcpy(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice), "batched launch map")) {
+    for (int e = 0; e < n_epochs && rc == STD_OK; ++e) {
+      for (int i = 0; i < n && rc == STD_OK; ++i) {
+        stdecomp_handle* h = hs[i];
+        if (h->sched_epoch != h->epoch) rc = run_schedule(h, h->epoch);
+        if (rc == STD_OK) hipck(hipStreamSynchronize(h->stream), "schedule");
+      }
+      if (rc != STD_OK) break;
+      hipck(hipEventRecord(h0->ev[1], h0->stream), "event");
+      for (int64_t c0 = 0; c0 < max_nb && rc == STD_OK; c0 += kBatchesPerLaunch) {
+        for (int i = 0; i < n; ++i) {
+          stdecomp_handle* h = hs[i];
+          args[i] = chain_args(h);
+          args[i].b_begin = c0 < h->nb ? c0 : h->nb;
+          args[i].b_end = c0 + kBatchesPerLaunch < h->nb ? c0 + kBatchesPerLaunch : h->nb;
+          hipck(hipMemsetAsync(h->err, 0, sizeof(int), h0->stream), "memset");
+          hipck(hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h0->stream), "memset");
+        }
+        hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
+              "batched launch arguments");
+        hipck(stdk::launch_chain_multi(h0->s, h0->dtype == STD_DTYPE_BF16, dargs, dmap, total_w, h0->threads, lds,
+                                       h0->stream),
+              "batched chain launch");
+        hipck(hipStreamSynchronize(h0->stream), "batched chain launch");  // (args reused next)
+      }
+      hipck(hipEventRecord(h0->ev[2], h0->stream), "event");
+      hipck(hipStreamSynchronize(h0->stream), "event");
+      float ms = 0.f;
+      hipck(hipEventElapsedTime(&ms, h0->ev[1], h0->ev[2]), "event");
+      for (int i = 0; i < n && rc == STD_OK; ++i) {
+        stdecomp_handle* h = hs[i];
+        int err = 0;
+        hipck(hipMemcpy(&err, h->err, sizeof(int), hipMemcpyDeviceToHost), "error flag");
+        if (err) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+        acc[i].epochs_run++;
+        acc[i].updates += h->T;
+        acc[i].minibatches += h->nb;
+        acc[i].chain_seconds += ms * 1e-3;  // (the whole batched launch)
+        acc[i].device_seconds += ms * 1e-3;
+        acc[i].chain_launches += (max_nb + kBatchesPerLaunch - 1) / kBatchesPerLaunch;
+        acc[i].flops_alg += (double)h->T * (2.0 * h->s.N + 4.0) * h->s.P;
+        h->epoch++;
+      }
+    }
+  }
+  hipFree(dargs);
+  hipFree(dmap);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) {
+    if (st) st[i] = acc[i];
+    int r2 = check_finite(hs[i]);
+    if (r2) return r2;
+  }
+  return STD_OK;
+}
+
 int stdecomp_run_minibatches(stdecomp_handle* h, int64_t epoch, int64_t b_begin, int64_t b_end,
                              stdecomp_epoch_stats* st) {
   if (!h) return STD_E_STATE;

@@ -341,3 +341,45 @@ def test_rows_after_minibatches(lib, oracle_mod, dims, ranks, chunk):
             errs = [float(np.max(np.abs(a - r))) for a, r in zip(A, ref.A)] + [float(np.max(np.abs(G - ref.G)))]
             say("  minibatches", nb, "split launches" if split else "one launch", "max abs errors", errs)
             assert max(errs) <= ROW_TOL, errs
+
+
+# ------------------------------------------------ several models, one launch
+# stdecomp_epoch_batched runs the chains of independent models in one
+# launch; every model must end exactly where it ends alone (the same chain
+# code, arguments and workgroup count), and a batch the single launch cannot
+# take (mixed ranks) falls back to running the models one after another.
+BATCH_SETS = {
+    "n3_j4": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((120, 90, 60), (4, 4, 4), 9000, 256, 32),
+              ((300, 40, 70), (4, 4, 4), 15000, 1024, 128), ((50, 50, 50), (4, 4, 4), 3000, 128, 64)],
+    "n4_j8": [((60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 64), ((40, 30, 20, 15), (8, 8, 8, 8), 8000, 512, 128)],
+    "mixed_ranks_fallback": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((80, 70, 60), (5, 5, 5), 6000, 256, 64)],
+}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("name", list(BATCH_SETS))
+def test_batched_models_match_alone(lib, name, dtype):
+    models = BATCH_SETS[name]
+    say("batched", name, dtype)
+    inputs = []
+    for k, (dims, ranks, nnz, M, chunk) in enumerate(models):
+        idx, vals = synth.random_tiny(len(dims), dims, ranks, nnz, seed=40 + k, skew=1.2)
+        A0, G0 = synth.init_params(dims, ranks, seed=50 + k)
+        inputs.append((dims, ranks, idx, (vals * 0.5).astype(np.float32), A0, G0, M, chunk))
+    alone = []
+    for (dims, ranks, idx, vals, A0, G0, M, chunk) in inputs:
+        h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.02, seed=77, chunk=chunk, dtype=dtype)
+        h.epoch(2)
+        alone.append(h.get_params())
+        h.close()
+    hs = [make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.02, seed=77, chunk=chunk, dtype=dtype)
+          for (dims, ranks, idx, vals, A0, G0, M, chunk) in inputs]
+    stats = lib.epoch_batched(hs, 2)
+    mixed = [h.get_params() for h in hs]
+    for h in hs:
+        h.close()
+    for k, ((A1, G1), (A2, G2), s) in enumerate(zip(alone, mixed, stats)):
+        assert s["epochs_run"] == 2
+        diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A1, A2)] + [float(np.max(np.abs(G1 - G2)))])
+        say("  model", k, "max |alone - batched|", diff)
+        assert diff == 0.0, (k, diff)
