@@ -141,6 +141,29 @@ def planted_uniform(dims=(1000, 1000, 1000), ranks=(5, 5, 5), nnz=100_000, sigma
                     name="planted_uniform")
 
 
+def planted_batch(n=64, ranks_choice=(4, 8, 16), log_dims=(3.0, 6.0), log_nnz=(4.0, 7.0), sigma=0.01,
+                  seed=1004, device=None, holdout=0.0):
+    """Many independent three-mode tensors: mode sizes floor(10^U(log_dims)),
+    entry counts floor(10^U(log_nnz)), uniform indices, equal ranks J drawn
+    from ``ranks_choice``, values from each tensor's planted model plus
+    N(0, sigma^2) noise."""
+    rng = _rng(seed)
+    out = []
+    for t in range(n):
+        dims = tuple(int(10 ** rng.uniform(*log_dims)) for _ in range(3))
+        nnz = int(10 ** rng.uniform(*log_nnz))
+        J = int(rng.choice(ranks_choice))
+        ranks = (J, J, J)
+        idx = np.stack([uniform_indices(rng, I, nnz) for I in dims])
+        A, G = planted_model(rng, dims, ranks)
+        noise = rng.standard_normal(nnz) * sigma
+        clean = evaluate_planted(A, G, ranks, idx) if device is None else evaluate_planted_device(A, G, ranks, idx, device)
+        vals = (clean + noise).astype(np.float32)
+        mask = split_holdout(rng, nnz, holdout) if holdout > 0 else np.zeros(nnz, bool)
+        out.append(Workload(dims, ranks, idx, vals, mask, planted=(A, G), noise=noise[~mask], name="planted_batch_%d" % t))
+    return out
+
+
 RATING_PROBS = (0.05, 0.10, 0.25, 0.35, 0.25)
 
 
