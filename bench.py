@@ -41,9 +41,11 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=60,
                     help="minibatches of the CPU oracle baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "chain_traffic.json"))
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--duration", type=float, default=10.0, help="(c5) seconds of job arrivals")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: Netflix-shaped ratings (default); c3: 4-order planted power-law tensor, FP32 vs BF16; "
-                         "c4: 64 independent planted tensors, batched launches vs one model at a time")
+                         "c4: 64 independent planted tensors, batched launches vs one model at a time; "
+                         "c5: serving loop (Poisson jobs and queries), p50/p99 latency")
     ap.add_argument("--epochs", type=int, default=5, help="(c3) epochs per precision")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
@@ -72,6 +74,9 @@ def main():
         return
     if args.config == "c4":
         run_c4(args)
+        return
+    if args.config == "c5":
+        run_c5(args)
         return
 
     import numpy as np
@@ -333,6 +338,95 @@ def run_c4(args):
                                  "sample": "one epoch of each of the 4 smallest tensors (%d updates), FP64 C, one thread"
                                            % upd}, **host_cpu())}
     print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """Serving: decomposition jobs arrive by a Poisson process (20/s for
+    --duration seconds), each a planted tensor of order 3 or 4 with
+    10^U(4,6) entries, mode sizes 10^U(3,5), equal ranks from {4, 8, 16}
+    (order 4: {4, 8}), N(0, 0.01^2) noise, 5 epochs, M = 1024; completion
+    queries (random index tuples of a resident model) arrive at 10^5/s.
+    Jobs are admitted by device footprint and advance one epoch per round,
+    jobs with the same kernel in one batched launch; queries are answered
+    between rounds.  value = nonzero-updates/s over the whole run."""
+    import numpy as np
+    import torch
+    from paper_2012_03550_amd import serve, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(1005)
+    D = args.duration
+    jobs, t = [], 0.0
+    t_gen = time.time()
+    while True:
+        t += rng.exponential(1 / 20.0)
+        if t > D:
+            break
+        N = int(rng.choice([3, 4]))
+        J = int(rng.choice([4, 8, 16] if N == 3 else [4, 8]))
+        dims = tuple(int(10 ** rng.uniform(3, 5)) for _ in range(N))
+        nnz = int(10 ** rng.uniform(4, 6))
+        idx = np.stack([synth.uniform_indices(rng, I, nnz) for I in dims])
+        A, G = synth.planted_model(rng, dims, (J,) * N)
+        clean = synth.evaluate_planted_device(A, G, (J,) * N, idx, "cuda")
+        vals = (clean + rng.standard_normal(nnz) * 0.01).astype(np.float32)
+        jobs.append(serve.Job(len(jobs), t, dims, (J,) * N, idx, vals, epochs=5, seed=3005 + len(jobs)))
+    qarr = np.sort(rng.uniform(0.0, D, rng.poisson(1e5 * D)))
+    log("trace: %d jobs (%d entries), %d queries; generated in %.1fs" %
+        (len(jobs), sum(j.idx.shape[1] for j in jobs), qarr.size, time.time() - t_gen))
+    srv = serve.Server(hbm_budget=100 << 30, dtype=args.dtype)
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0  # noqa: E731
+    ji = qi = 0
+    qlat = []
+    rounds = 0
+    while ji < len(jobs) or srv.pending or srv.active:
+        now = clock()
+        while ji < len(jobs) and jobs[ji].arrival <= now:
+            srv.submit(jobs[ji])
+            ji += 1
+        srv.admit(now)
+        if srv.active:
+            srv.round(clock)
+            rounds += 1
+        elif ji < len(jobs):
+            time.sleep(max(0.0, jobs[ji].arrival - clock()))
+        hi = int(np.searchsorted(qarr, clock(), side="right"))
+        if hi > qi and srv.answer(hi - qi, rng):
+            done = clock()
+            qlat.extend((done - qarr[qi:hi]).tolist())
+            qi = hi
+        if rounds and rounds % 50 == 0:
+            log("round %d: t=%.1fs, %d done, %d active, %d waiting" % (rounds, clock(), len(srv.done),
+                                                                    len(srv.active), len(srv.pending)))
+        if clock() > D + 600:
+            log("stopping: the run exceeded its time limit")
+            break
+    wall = clock()
+    jl = [j.finished - j.arrival for j in srv.done]
+    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": round(srv.updates / wall, 1),
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": rounds, "warmup": 0, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": "serving: Poisson jobs 20/s for %gs (order 3-4, 10^U(4,6) entries, J in {4,8,16}, "
+                                  "5 epochs, M=1024) + completion queries 1e5/s" % D,
+                      "jobs": len(jobs), "queries": int(qarr.size)},
+           "serve": {"jobs_done": len(srv.done), "job_latency_s_p50": percentile_or_none(jl, 50),
+                     "job_latency_s_p99": percentile_or_none(jl, 99),
+                     "queries_answered": len(qlat), "query_latency_ms_p50": ms_or_none(percentile_or_none(qlat, 50)),
+                     "query_latency_ms_p99": ms_or_none(percentile_or_none(qlat, 99)),
+                     "job_train_rmse_median": percentile_or_none([j.rmse for j in srv.done], 50),
+                     "wall_s": round(wall, 3), "rounds": rounds}}
+    print(json.dumps(out), flush=True)
+
+
+def percentile_or_none(xs, p):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(xs, np.float64), p)), 6) if len(xs) else None
+
+
+def ms_or_none(x):
+    return None if x is None else round(1e3 * x, 3)
 
 
 def latency_bound(h, M, N, chain_rate):
