@@ -378,8 +378,17 @@ def run_c5(args):
     srv = serve.Server(hbm_budget=100 << 30, dtype=args.dtype)
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0  # noqa: E731
-    ji = qi = 0
     qlat = []
+    qpos = [0]
+
+    def answer_queries():  # every query that has arrived, if a model is resident
+        hi = int(np.searchsorted(qarr, clock(), side="right"))
+        if hi > qpos[0] and srv.answer(hi - qpos[0], rng):
+            done = clock()
+            qlat.extend((done - qarr[qpos[0]:hi]).tolist())
+            qpos[0] = hi
+
+    ji = 0
     rounds = 0
     while ji < len(jobs) or srv.pending or srv.active:
         now = clock()
@@ -388,15 +397,11 @@ def run_c5(args):
             ji += 1
         srv.admit(now)
         if srv.active:
-            srv.round(clock)
+            srv.round(clock, answer_queries)
             rounds += 1
         elif ji < len(jobs):
             time.sleep(max(0.0, jobs[ji].arrival - clock()))
-        hi = int(np.searchsorted(qarr, clock(), side="right"))
-        if hi > qi and srv.answer(hi - qi, rng):
-            done = clock()
-            qlat.extend((done - qarr[qi:hi]).tolist())
-            qi = hi
+        answer_queries()
         if rounds and rounds % 50 == 0:
             log("round %d: t=%.1fs, %d done, %d active, %d waiting" % (rounds, clock(), len(srv.done),
                                                                     len(srv.active), len(srv.pending)))

@@ -80,8 +80,10 @@ class Server:
             self.active.append(job)
             self.pending.pop(0)
 
-    def round(self, clock):
-        """One epoch of every admitted job; retires the jobs that finish."""
+    def round(self, clock, between=None):
+        """One epoch of every admitted job; retires the jobs that finish.
+        ``between()`` (if given) runs after each batched launch, so queries
+        need not wait for the whole round."""
         groups = {}
         for job in self.active:
             groups.setdefault(job.key(self.dtype), []).append(job)
@@ -95,6 +97,8 @@ class Server:
                         for j in batch:
                             j.done_epochs += 1
                             self.updates += j.idx.shape[1]
+                        if between is not None:
+                            between()
                     batch, wgs = [], 0
                 if job is not None:
                     batch.append(job)
