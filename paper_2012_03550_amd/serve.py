@@ -49,8 +49,9 @@ class Job:
 
 
 class Server:
-    def __init__(self, hbm_budget, max_workgroups=256, chunk=128, dtype="f32", lr=0.01, lam=0.01):
+    def __init__(self, hbm_budget, max_workgroups=256, chunk=128, dtype="f32", lr=0.01, lam=0.01, on_finish=None):
         self.budget = hbm_budget
+        self.on_finish = on_finish  # called with a finished job while its handle is still open
         self.max_wgs = max_workgroups
         self.chunk = chunk
         self.dtype = dtype
@@ -108,6 +109,8 @@ class Server:
             if job.done_epochs >= job.epochs:
                 job.finished = now
                 job.rmse = job.handle.loss()["rmse"]
+                if self.on_finish is not None:
+                    self.on_finish(job)
                 job.handle.close()
                 job.handle = None
                 self.used -= job.need

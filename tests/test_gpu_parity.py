@@ -383,3 +383,35 @@ def test_batched_models_match_alone(lib, name, dtype):
         diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A1, A2)] + [float(np.max(np.abs(G1 - G2)))])
         say("  model", k, "max |alone - batched|", diff)
         assert diff == 0.0, (k, diff)
+
+
+def test_serving_loop_results_match_alone(lib):
+    """Jobs that train through the serving loop (admission, rounds of
+    batched epochs, retirement) end exactly where they end alone."""
+    from paper_2012_03550_amd import serve
+    say("serving loop")
+    specs = [((200, 150, 100), (4, 4, 4), 20000), ((120, 90, 60), (4, 4, 4), 9000), ((60, 50, 30, 20), (8, 8, 8, 8), 8000),
+             ((80, 70, 60), (5, 5, 5), 6000)]
+    jobs = []
+    for k, (dims, ranks, nnz) in enumerate(specs):
+        idx, vals = synth.random_tiny(len(dims), dims, ranks, nnz, seed=60 + k, skew=1.2)
+        jobs.append(serve.Job(k, 0.0, dims, ranks, idx, (vals * 0.5).astype(np.float32), epochs=2 + (k % 2),
+                              batch=512, seed=500 + 7 * k))
+    final = {}
+    srv = serve.Server(hbm_budget=1 << 34, chunk=64, on_finish=lambda j: final.__setitem__(j.jid, j.handle.get_params()))
+    for j in jobs:
+        srv.submit(j)
+    srv.admit(0.0)
+    while srv.active:
+        srv.round(lambda: 0.0)
+    assert len(srv.done) == len(jobs)
+    for j in jobs:
+        h = lib.Stdecomp(j.dims, j.ranks, j.idx, j.vals, batch=512, lr_factor=0.01, lr_core=0.01, lam_factor=0.01,
+                         lam_core=0.01, seed_sample=j.seed, seed_init=j.seed + 1, chunk=64)
+        h.epoch(j.epochs)
+        A, G = h.get_params()
+        h.close()
+        A2, G2 = final[j.jid]
+        diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A, A2)] + [float(np.max(np.abs(G - G2)))])
+        say("  job", j.jid, "epochs", j.epochs, "max |alone - served|", diff)
+        assert diff == 0.0
