@@ -415,3 +415,19 @@ def test_serving_loop_results_match_alone(lib):
         diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A, A2)] + [float(np.max(np.abs(G - G2)))])
         say("  job", j.jid, "epochs", j.epochs, "max |alone - served|", diff)
         assert diff == 0.0
+
+
+def test_chunk_tuner(lib):
+    """The tuner times each candidate chunk that fits and returns the fastest;
+    a handle built with it trains."""
+    from paper_2012_03550_amd import tune
+    dims, ranks = (300, 200, 100), (8, 8, 8)
+    idx, vals = synth.random_tiny(3, dims, ranks, 30000, seed=70, skew=1.1)
+    best, times = tune.tune_chunk(dims, ranks, idx, vals, 1024, candidates=(32, 64, 128, 256), minibatches=16)
+    say("tuner", times, "->", best)
+    assert best in times and times[best] == min(times.values()) and len(times) >= 2
+    assert tune.tune_chunk(dims, ranks, idx, vals, 1024)[0] == best  # cached
+    h = lib.Stdecomp(dims, ranks, idx, vals, batch=1024, chunk=best)
+    assert h.info()["chunk"] == best
+    h.epoch(1)
+    h.close()

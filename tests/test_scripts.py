@@ -12,7 +12,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SCRIPTS = ["bench.py", "__graft_entry__.py", os.path.join("paper_2012_03550_amd", "binding.py"),
-           os.path.join("paper_2012_03550_amd", "synth.py"), os.path.join("paper_2012_03550_amd", "serve.py")]
+           os.path.join("paper_2012_03550_amd", "synth.py"), os.path.join("paper_2012_03550_amd", "serve.py"),
+           os.path.join("paper_2012_03550_amd", "tune.py")]
 
 
 def _bound_names(node):
