@@ -52,7 +52,6 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
   // round to nearest even (gfx950 converts in hardware, NaN stays NaN)
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
-__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float((uint32_t)bf16_bits(f) << 16); }
 __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ---------------------------------------------------------------------------
@@ -1840,7 +1839,6 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   return off * 4;
 }
 
-size_t chain_lds_bytes(const ChainArgs& a, int threads) { return (size_t)a.lay.total * 4; }
 
 template <int JU, int NU, int BFI>
 hipError_t launch_chain_t(const ChainArgs& a, int threads, size_t bytes, hipStream_t st) {

@@ -140,7 +140,6 @@ hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const
 // Fills a.lay and a.pt and the index maps (aux, a.lay.aux_len ints); returns
 // the LDS bytes of one workgroup, or 0 if the request is inconsistent.
 size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
-size_t chain_lds_bytes(const ChainArgs& a, int threads);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st);
 // Several chains of one kernel variant (equal rank 4, 8 or 16; the same order
