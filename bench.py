@@ -42,10 +42,11 @@ def main():
                     help="minibatches of the CPU oracle baseline (0: skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "chain_traffic.json"))
     ap.add_argument("--duration", type=float, default=10.0, help="(c5) seconds of job arrivals")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ranks"],
                     help="c2: Netflix-shaped ratings (default); c3: 4-order planted power-law tensor, FP32 vs BF16; "
                          "c4: 64 independent planted tensors, batched launches vs one model at a time; "
-                         "c5: serving loop (Poisson jobs and queries), p50/p99 latency")
+                         "c5: serving loop (Poisson jobs and queries), p50/p99 latency; "
+                         "ranks: core-rank sweep J = 4..24 on a ratings tensor")
     ap.add_argument("--epochs", type=int, default=5, help="(c3) epochs per precision")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
@@ -77,6 +78,9 @@ def main():
         return
     if args.config == "c5":
         run_c5(args)
+        return
+    if args.config == "ranks":
+        run_ranks(args)
         return
 
     import numpy as np
@@ -432,6 +436,51 @@ def percentile_or_none(xs, p):
 
 def ms_or_none(x):
     return None if x is None else round(1e3 * x, 3)
+
+
+def run_ranks(args):
+    """Core-rank sweep: the ratings workload of config 2 at 20M entries, equal
+    ranks J in {4, 6, 8, 10, 12, 16, 20, 24}, M = 4096, two epochs each from
+    the scaled initialisation; updates/s of the second epoch and the
+    held-out RMSE after it (a rank whose chain does not fit one workgroup's
+    LDS is reported as such)."""
+    import numpy as np
+    import torch
+    from paper_2012_03550_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    nnz = 20_000_000
+    rows = []
+    wl = synth.ratings_zipf(nnz=nnz)
+    for J in (4, 6, 8, 10, 12, 16, 20, 24):
+        try:
+            h = binding.Stdecomp(wl.dims, (J, J, J), wl.train_idx, wl.train_vals, batch=4096, seed_sample=3002,
+                                 seed_init=2002, dtype=args.dtype)
+        except binding.StdecompError as e:
+            rows.append({"J": J, "fits": False, "error": str(e)})
+            log("J=%d: %s" % (J, e))
+            continue
+        h.epoch(1)
+        st = h.epoch(1)
+        rmse = h.loss(wl.test_idx, wl.test_vals)["rmse"]
+        info = h.info()
+        h.close()
+        per_mb = st["chain_seconds"] / st["minibatches"]
+        rows.append({"J": J, "fits": True, "updates_per_s": round(st["updates"] / st["device_seconds"], 1),
+                     "us_per_minibatch": round(per_mb * 1e6, 2), "heldout_rmse": round(rmse, 6),
+                     "kernel_variant": info["variant"], "workgroups": info["workgroups"],
+                     "mfma_TFs": round(st["flops_alg"] / st["chain_seconds"] / 1e12, 4)})
+        log("J=%d: %.3e updates/s, %.1f us per minibatch, held-out RMSE %.5f" % (J, rows[-1]["updates_per_s"],
+                                                                             per_mb * 1e6, rmse))
+    best = max((r["updates_per_s"] for r in rows if r.get("fits")), default=None)
+    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": rows[3].get("updates_per_s") if len(rows) > 3 else best,
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": "ratings_zipf 480000x18000x2000 at 20M entries, equal ranks J = 4..24, M=4096; "
+                                  "value = J=10", "entries": nnz},
+           "sweep": rows}
+    print(json.dumps(out), flush=True)
 
 
 def latency_bound(h, M, N, chain_rate):
