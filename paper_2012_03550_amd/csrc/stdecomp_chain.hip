@@ -1246,9 +1246,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
   int par = 0;   // carry parity of the current phase
   bool first = true;
 
-  LaneRec<NM> cur;
-  if (a.b_begin < a.b_end) load_lane_rec<NM>(a, w, N, a.b_begin, 0, cur);
-  else cur.valid = false;
+  // records of this phase (cur) and the next (nx); the one after is read in
+  // each phase's barrier window
+  LaneRec<NM> cur, nx;
+  if (a.b_begin < a.b_end) {
+    load_lane_rec<NM>(a, w, N, a.b_begin, 0, cur);
+    load_lane_rec<NM>(a, w, N, a.b_begin, 1, nx);
+  } else {
+    cur.valid = nx.valid = false;
+  }
   int bsel = 0;  // which row buffer holds the current sub-step's rows
   float an_cur[JR], an_nxt[JR];  // BF16 mode: FP32 master row of the lane's own-mode row
 #pragma unroll
@@ -1324,7 +1330,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       }
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // the rows written straight into LDS have landed
       __syncthreads();
-      // the next phase's record (read-only; its latency overlaps this phase)
+      // the next phase (its record nx was read one phase ahead)
       int nph = ph + 1;
       int64_t nbb = b;
       if (nph > N) {
@@ -1332,9 +1338,6 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
         ++nbb;
       }
       const bool has_next = nbb < a.b_end;
-      LaneRec<NM> nx;
-      if (has_next) load_lane_rec<NM>(a, w, N, nbb, nph, nx);
-      else nx.valid = false;
 
       // ---- 2. core: finish the core step of this minibatch
       if (ph == 1 && CORE2) {
@@ -1573,10 +1576,23 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       }
       if (!L.tb_all && has_next && nph != 1)  // (this phase's contraction is done: the arrival synchronised)
         build_table_arith<JR, BF, EXACT, TS>(a.pt[nph], Gs, hmap + a.pt[nph].hm_off, TB);
+      // the record of the phase after next (read-only schedule data)
+      LaneRec<NM> nx2;
+      {
+        int ph2 = nph + 1;
+        int64_t b2 = nbb;
+        if (ph2 > N) {
+          ph2 = 0;
+          ++b2;
+        }
+        if (b2 < a.b_end) load_lane_rec<NM>(a, w, N, b2, ph2, nx2);
+        else nx2.valid = false;
+      }
       if (!barrier_wait(a, passed, misc + 7)) return;
       first = false;
       bsel ^= 1;
       cur = nx;
+      nx = nx2;
 #pragma unroll
       for (int j = 0; j < JR; ++j) an_cur[j] = an_nxt[j];
       ppar = par;
