@@ -697,7 +697,7 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
   int* dmap = nullptr;
   if (hipMalloc((void**)&dargs, sizeof(stdk::ChainArgs) * n) != hipSuccess ||
       hipMalloc((void**)&dmap, sizeof(int) * map.size()) != hipSuccess) {
-    hipFree(dargs);
+    (void)hipFree(dargs);
     return fail(h0, STD_E_NOMEM, "batched launch: device allocation failed");
   }
   std::vector<stdk::ChainArgs> args((size_t)n);
@@ -752,8 +752,8 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
       }
     }
   }
-  hipFree(dargs);
-  hipFree(dmap);
+  (void)hipFree(dargs);
+  (void)hipFree(dmap);
   if (rc) return rc;
   for (int i = 0; i < n; ++i) {
     if (st) st[i] = acc[i];
