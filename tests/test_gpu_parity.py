@@ -431,3 +431,18 @@ def test_chunk_tuner(lib):
     assert h.info()["chunk"] == best
     h.epoch(1)
     h.close()
+
+
+def test_barrier_probe(lib):
+    """The grid-barrier timing aid returns a positive time and rejects bad
+    arguments."""
+    dims, ranks = (200, 150, 100), (4, 4, 4)
+    idx, vals = synth.random_tiny(3, dims, ranks, 20000, seed=9)
+    h = lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=64)
+    t = h.barrier_us(500)
+    say("barrier", h.info()["workgroups"], "workgroups:", t, "us")
+    assert 0.0 < t < 1000.0
+    with pytest.raises(lib.StdecompError):
+        h.barrier_us(0)
+    h.epoch(1)  # the chain still runs after the probe
+    h.close()
