@@ -40,7 +40,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-batches", type=int, default=60,
                     help="minibatches of the CPU oracle baseline (0: skip)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "chain_traffic.json"))
+    ap.add_argument("--traffic-json", default=None,
+                    help="counter record of the chain (default: profiles/chain_traffic.json for FP32, "
+                         "profiles/chain_traffic_bf16.json for BF16)")
     ap.add_argument("--duration", type=float, default=10.0, help="(c5) seconds of job arrivals")
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ranks"],
                     help="c2: Netflix-shaped ratings (default); c3: 4-order planted power-law tensor, FP32 vs BF16; "
@@ -135,8 +137,10 @@ def main():
     achieved = flops_per_launch / avg_launch / 1e12
     peak = PEAK["bf16_TFs"] if args.dtype == "bf16" else PEAK["fp32_TFs"]
     traffic = None
-    if os.path.exists(args.traffic_json):
-        tj = json.load(open(args.traffic_json))
+    tpath = args.traffic_json or os.path.join(
+        ROOT, "profiles", "chain_traffic.json" if args.dtype == "f32" else "chain_traffic_%s.json" % args.dtype)
+    if os.path.exists(tpath):
+        tj = json.load(open(tpath))
         if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("dtype") == args.dtype:
             traffic = tj.get("bytes_per_launch")
     roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
