@@ -343,8 +343,9 @@ def run_c4(args):
                       "tensors": len(wls), "entries": int(total), "batch": M, "chunk": chunk},
            "f32": res["f32"], "bf16": res["bf16"],
            "cpu_baseline": dict({"value": round(upd / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
-                                 "sample": "one epoch of each of the 4 smallest tensors (%d updates), FP64 C, one thread"
-                                           % upd}, **host_cpu())}
+                                 "sample": "one epoch of each of the 4 smallest tensors (%d updates), FP64 C, one "
+                                           "thread, from the host initialiser's own draw (a timing sample)" % upd},
+                                **host_cpu())}
     print(json.dumps(out), flush=True)
 
 
