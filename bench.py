@@ -186,7 +186,7 @@ def run_c3(args):
     to the zero saddle and stays there; at lr = 0.1 it diverges in the first
     epoch), ``--epochs`` epochs in FP32 and in BF16 from the same initial
     parameters.  Precision: the FP64 oracle, the FP32 chain and the BF16 chain
-    run the same first 100 minibatches of epoch 0 and their held-out RMSE is
+    run the same first 200 minibatches of epoch 0 and their held-out RMSE is
     compared on a 200,000-entry sample of the held-out set."""
     import numpy as np
     import torch
@@ -199,7 +199,7 @@ def run_c3(args):
     t = time.time()
     wl = synth.planted_powerlaw(nnz=nnz, device="cuda")
     log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
-    M, lr, lam, prefix, sample = 8192, 0.05, 1e-4, 100, 200_000
+    M, lr, lam, prefix, sample = 8192, 0.05, 1e-4, 200, 200_000
     test_idx = torch.from_numpy(wl.test_idx).cuda()
     test_vals = torch.from_numpy(wl.test_vals).cuda()
     s_idx = np.ascontiguousarray(wl.test_idx[:, :sample])
