@@ -73,7 +73,8 @@ typedef struct {
   int32_t inputs_on_device; /* 1: problem.idx / problem.vals are device pointers */
   void* stream;           /* hipStream_t to run on, or NULL for a private stream */
   int32_t chain_chunk;    /* entries per workgroup per sub-step; 0: automatic, about M/32,
-                             halved while chunk * prod(J) > 2^19 or the rows of one
+                             halved while chunk * prod(J) > 2^18 (three modes; 2^19
+                             otherwise) or the rows of one
                              workgroup exceed its LDS */
   int32_t reserved[15];   /* must be zero */
 } stdecomp_options;

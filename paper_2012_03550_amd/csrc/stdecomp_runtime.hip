@@ -136,12 +136,14 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
   int chunk = chunk_req;
   if (chunk <= 0) {
     // about 32 workgroups for large minibatches, at least 64 entries each;
-    // for large cores more, smaller chunks (at most 2^19 core-sized
-    // contractions per workgroup and sub-step)
+    // for large cores more, smaller chunks (at most 2^18 core-sized
+    // contractions per workgroup and sub-step for three modes, 2^19 for more:
+    // the two-stage contraction of those kernels gains from longer chunks)
     chunk = (int)((h->M + 31) / 32);
     if (chunk < 64) chunk = 64;
     chunk = ((chunk + 63) / 64) * 64;
-    while (chunk > 64 && (int64_t)chunk * s.P > (1 << 19) && (h->M + chunk / 2 - 1) / (chunk / 2) <= h->num_cus)
+    const int64_t lim = s.N == 3 ? (1 << 18) : (1 << 19);
+    while (chunk > 64 && (int64_t)chunk * s.P > lim && (h->M + chunk / 2 - 1) / (chunk / 2) <= h->num_cus)
       chunk /= 2;
   }
   if (chunk > stdk::kChainThreads) chunk = stdk::kChainThreads;
