@@ -249,18 +249,23 @@ def run_c3(args):
                       "heldout_rmse_per_epoch": rmse,
                       "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
                       "chain_chunk": info["chunk"]}
-    oracle.build()
-    ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
-    log("oracle: running %d minibatches of epoch 0" % prefix)
-    t = time.perf_counter()
-    ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3003, epoch0=0, n_epochs=1, max_batches=prefix)
-    dt = time.perf_counter() - t
-    orc = ref.loss(s_idx, s_vals)["rmse"]
-    log("oracle: %d minibatches in %.1fs, sample held-out RMSE %.6f" % (prefix, dt, orc))
-    precision = {"prefix_minibatches": prefix, "heldout_sample": sample, "rmse_oracle_f64": orc,
-                 "rmse_f32": res["f32"]["prefix_heldout_rmse_sample"], "rmse_bf16": res["bf16"]["prefix_heldout_rmse_sample"],
-                 "f32_rel_gap": (res["f32"]["prefix_heldout_rmse_sample"] - orc) / orc,
-                 "bf16_rel_gap": (res["bf16"]["prefix_heldout_rmse_sample"] - orc) / orc}
+    precision = cpu = None
+    if args.cpu_batches > 0:  # (--cpu-batches 0: no oracle, for profiling runs)
+        oracle.build()
+        ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+        log("oracle: running %d minibatches of epoch 0" % prefix)
+        t = time.perf_counter()
+        ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3003, epoch0=0, n_epochs=1, max_batches=prefix)
+        dt = time.perf_counter() - t
+        orc = ref.loss(s_idx, s_vals)["rmse"]
+        log("oracle: %d minibatches in %.1fs, sample held-out RMSE %.6f" % (prefix, dt, orc))
+        precision = {"prefix_minibatches": prefix, "heldout_sample": sample, "rmse_oracle_f64": orc,
+                     "rmse_f32": res["f32"]["prefix_heldout_rmse_sample"],
+                     "rmse_bf16": res["bf16"]["prefix_heldout_rmse_sample"],
+                     "f32_rel_gap": (res["f32"]["prefix_heldout_rmse_sample"] - orc) / orc,
+                     "bf16_rel_gap": (res["bf16"]["prefix_heldout_rmse_sample"] - orc) / orc}
+        cpu = dict({"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
+                    "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix}, **host_cpu())
     out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": res["f32"]["updates_per_s"],
            "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.epochs, "warmup": 0, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -269,9 +274,7 @@ def run_c3(args):
                                   "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
                       "train_entries": int(wl.nnz), "batch": M},
            "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
-           "cpu_baseline": dict({"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1,
-                                 "kind": "oracle", "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix},
-                                **host_cpu())}
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
