@@ -214,6 +214,9 @@ def run_c3(args):
         h.run_minibatches(0, 0, prefix)
         prefix_rmse = h.loss(s_idx, s_vals)["rmse"]
         h.set_params(A0, G0)
+        A1, G1 = h.get_params()
+        if not (all(np.array_equal(a, b) for a, b in zip(A0, A1)) and np.array_equal(G0, G1)):
+            raise RuntimeError("c3 %s: parameters read back after set_params differ from those set" % dtype)
         h.set_epoch(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

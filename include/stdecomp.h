@@ -146,7 +146,10 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
                   stdecomp_loss_out* out);
 
 /* Copy the FP32 master parameters out of / into the handle (host memory).
- * A[n] points to I_n x J_n row-major floats; G to prod(J) floats (j_1 fastest). */
+ * A[n] points to I_n x J_n row-major floats; G to prod(J) floats (j_1 fastest).
+ * Both are synchronous: each factor goes in one contiguous copy (rows are
+ * padded or unpacked on the host), and set_params zeroes the row padding.
+ * Errors: STD_E_INVAL for NULL pointers, STD_E_DEVICE if a copy fails. */
 int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G);
 int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G);
 

@@ -847,10 +847,22 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
 int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G) {
   if (!h) return STD_E_STATE;
   if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
+  // one contiguous copy per factor (padded rows), unpacked on the host: a
+  // pitched copy from pageable memory goes row by row
+  std::vector<float> buf;
   for (int n = 0; n < h->s.N; ++n) {
     if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
-    HIPCHK(h, hipMemcpy2DAsync(A[n], (size_t)h->s.J[n] * 4, h->A[n], (size_t)h->s.Jp[n] * 4, (size_t)h->s.J[n] * 4,
-                               (size_t)h->s.I[n], hipMemcpyDeviceToHost, h->stream));
+    const int J = h->s.J[n], Jp = h->s.Jp[n];
+    const size_t rows = (size_t)h->s.I[n];
+    if (J == Jp) {
+      HIPCHK(h, hipMemcpyAsync(A[n], h->A[n], rows * J * 4, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+    } else {
+      buf.resize(rows * Jp);
+      HIPCHK(h, hipMemcpyAsync(buf.data(), h->A[n], buf.size() * 4, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      for (size_t i = 0; i < rows; ++i) std::memcpy(A[n] + i * J, buf.data() + i * Jp, (size_t)J * 4);
+    }
   }
   HIPCHK(h, hipMemcpyAsync(G, h->G, (size_t)h->s.P * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -860,10 +872,22 @@ int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G) {
 int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G) {
   if (!h) return STD_E_STATE;
   if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
-  for (int n = 0; n < h->s.N; ++n) {
+  // packed on the host into the padded row layout (padding stays zero) and
+  // sent in one contiguous copy per factor
+  for (int n = 0; n < h->s.N; ++n)
     if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
-    HIPCHK(h, hipMemcpy2DAsync(h->A[n], (size_t)h->s.Jp[n] * 4, A[n], (size_t)h->s.J[n] * 4, (size_t)h->s.J[n] * 4,
-                               (size_t)h->s.I[n], hipMemcpyHostToDevice, h->stream));
+  std::vector<float> buf;
+  for (int n = 0; n < h->s.N; ++n) {
+    const int J = h->s.J[n], Jp = h->s.Jp[n];
+    const size_t rows = (size_t)h->s.I[n];
+    if (J == Jp) {
+      HIPCHK(h, hipMemcpyAsync(h->A[n], A[n], rows * J * 4, hipMemcpyHostToDevice, h->stream));
+    } else {
+      buf.assign(rows * Jp, 0.f);
+      for (size_t i = 0; i < rows; ++i) std::memcpy(buf.data() + i * Jp, A[n] + i * J, (size_t)J * 4);
+      HIPCHK(h, hipMemcpyAsync(h->A[n], buf.data(), buf.size() * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // buf is reused for the next factor
   }
   HIPCHK(h, hipMemcpyAsync(h->G, G, (size_t)h->s.P * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
