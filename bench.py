@@ -222,6 +222,8 @@ def run_c3(args):
         t0 = time.perf_counter()
         dev = 0.0
         chain_s = 0.0
+        launches = 0
+        bytes_alg = 0.0
         rmse = []
         done = 0
         for e in range(args.epochs):
@@ -234,6 +236,8 @@ def run_c3(args):
             done += 1
             dev += st["device_seconds"]
             chain_s += st["chain_seconds"]
+            launches += st["chain_launches"]
+            bytes_alg += st["bytes_alg"]
             rmse.append(round(h.loss(test_idx, test_vals)["rmse"], 6))
             log("c3 %s epoch %d: chain %.3fs held-out RMSE %.5f" % (dtype, e, st["chain_seconds"], rmse[-1]))
         torch.cuda.synchronize()
@@ -247,8 +251,12 @@ def run_c3(args):
         res[dtype] = {"updates_per_s": round(wl.nnz * done / wall, 1) if done else None, "device_updates_per_s":
                       round(wl.nnz * done / dev, 1) if done else None,
                       "roofline": {"bound": "mfma", "achieved": round(ach, 4) if done else None, "peak": peak,
-                                   "unit": "TFLOP/s", "frac": round(ach / peak, 6) if done else None, "traffic": None,
-                                   "kernel": "k_chain", "chain_seconds": round(chain_s, 4), "latency_bound": lat},
+                                   "unit": "TFLOP/s", "frac": round(ach / peak, 6) if done else None,
+                                   "traffic": c3_traffic(dtype, wl.nnz), "kernel": "k_chain",
+                                   "chain_seconds": round(chain_s, 4), "chain_launches": launches,
+                                   "avg_launch_ms": round(chain_s / launches * 1e3, 3) if launches else None,
+                                   "alg_bytes_per_launch": int(bytes_alg / launches) if launches else None,
+                                   "latency_bound": lat},
                       "heldout_rmse_per_epoch": rmse,
                       "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
                       "chain_chunk": info["chunk"]}
@@ -514,6 +522,20 @@ def host_cpu():
     except OSError:
         pass
     return {"host_cpu": model, "host_threads": os.cpu_count()}
+
+
+def c3_traffic(dtype, train_entries):
+    """HBM bytes per chain launch of the config-3 epoch (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy-kernel factors), if the stored counter record
+    was taken on this kernel source, dtype and training-set size; else None."""
+    path = os.path.join(ROOT, "profiles", "chain_traffic_planted_powerlaw%s.json" % ("" if dtype == "f32" else "_bf16"))
+    if not os.path.exists(path):
+        return None
+    tj = json.load(open(path))
+    if (tj.get("kernel_source_hash") != kernel_source_hash() or tj.get("dtype") != dtype
+            or tj.get("train_entries") != train_entries):
+        return None
+    return tj.get("bytes_per_launch")
 
 
 def kernel_source_hash():
