@@ -159,6 +159,34 @@ def test_predict_and_loss(lib, oracle_mod, dims, ranks):
     h.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,ranks", [((7, 6), (5, 7)), ((10, 12, 9, 8), (2, 3, 2, 3)), ((40, 30, 20), (4, 4, 4)),
+                                        ((3000, 50, 20), (6, 6, 6))])
+def test_params_round_trip(lib, oracle_mod, dims, ranks, dtype):
+    """set_params / get_params return the FP32 masters bit for bit (rows of
+    J_n values stored at a padded stride), and a second set_params replaces
+    the first everywhere (predictions follow the second set)."""
+    say("params round trip", dims, ranks, dtype)
+    rng = np.random.default_rng(11)
+    idx, vals = synth.random_tiny(len(dims), dims, ranks, 2000, seed=6)
+    sets = []
+    for _ in range(2):
+        A = [rng.standard_normal((I, J)).astype(np.float32) for I, J in zip(dims, ranks)]
+        G = rng.standard_normal(int(np.prod(ranks))).astype(np.float32)
+        sets.append((A, G))
+    h = make_handle(lib, dims, ranks, idx, vals, sets[0][0], sets[0][1], 64, dtype=dtype)
+    for A, G in sets:
+        h.set_params(A, G)
+        A1, G1 = h.get_params()
+        assert all(np.array_equal(a, b) for a, b in zip(A, A1)) and np.array_equal(G, G1)
+    A, G = sets[1]
+    ref = oracle_mod.Model(dims, ranks, [a.astype(np.float64) for a in A], G.astype(np.float64))
+    q = np.stack([rng.integers(0, I, 1001) for I in dims]).astype(np.int32)
+    want = ref.predict(q)
+    assert np.max(np.abs(h.predict(q) - want)) <= 1e-5 * max(np.sqrt(np.mean(want ** 2)), 1e-3)
+    h.close()
+
+
 def test_predict_rejects_bad_index(lib):
     say("predict bad index")
     dims, ranks = (10, 10, 10), (2, 2, 2)
