@@ -71,8 +71,24 @@ def lib():
                               ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, _i64p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                               ctypes.c_int64, _i64p]
+        L.orc_kruskal_core.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p]
+        L.orc_kruskal_W.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, ctypes.c_int64, _i32p,
+                                    ctypes.c_int, ctypes.c_int, _f64p]
+        L.orc_kruskal_column_step.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, ctypes.c_int, _f64p,
+                                              ctypes.c_int64, _i32p, _f32p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double]
+        L.orc_kruskal_core_step.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _f64p,
+                                            ctypes.c_int64, _i32p, _f32p, ctypes.c_double, ctypes.c_double]
+        L.orc_step_kruskal.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _f64p,
+                                       ctypes.c_int64, _i32p, _f32p, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double]
+        L.orc_run_kruskal.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _f64p,
+                                      ctypes.c_int64, _i32p, _f32p, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64p, ctypes.c_uint64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p]
         for f in ("orc_perm", "orc_segments", "orc_predict", "orc_loss", "orc_core_step",
-                  "orc_mode_step", "orc_step", "orc_run"):
+                  "orc_mode_step", "orc_step", "orc_run", "orc_kruskal_core", "orc_kruskal_W",
+                  "orc_kruskal_column_step", "orc_kruskal_core_step", "orc_step_kruskal", "orc_run_kruskal"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -210,4 +226,88 @@ class Model:
         _check(lib().orc_run(*self._args(), T, _ptr(idx, _i32p), _ptr(vals, _f32p), M, gam_A, lam_A,
                              gam_G, lam_G, pp, ctypes.c_uint64(seed), epoch0, n_epochs, max_batches,
                              _ptr(done, _i64p)), "orc_run")
+        return int(done[0])
+
+
+# ----------------------------------------------------------- the Kruskal core
+def kruskal_core(ranks, B):
+    """Flat core (j_0 fastest) of the Kruskal product of the J_n x R matrices B."""
+    ranks = np.ascontiguousarray(ranks, np.int32)
+    R = int(np.asarray(B[0]).shape[1])
+    flatB = np.concatenate([np.ascontiguousarray(b, np.float64).reshape(-1) for b in B])
+    G = np.empty(int(np.prod(ranks)), np.float64)
+    _check(lib().orc_kruskal_core(len(ranks), _ptr(ranks, _i32p), R, _ptr(flatB, _f64p), _ptr(G, _f64p)),
+           "orc_kruskal_core")
+    return G
+
+
+class KruskalModel(Model):
+    """FP64 parameters of a sparse Tucker model whose core is the R_core
+    Kruskal product of the matrices B(n) (J_n x R); ``G`` always holds that
+    product."""
+
+    def __init__(self, dims, ranks, A, B):
+        self.R = int(np.asarray(B[0]).shape[1])
+        assert len(B) == len(dims) and all(np.asarray(b).shape == (J, self.R) for b, J in zip(B, ranks))
+        self.flatB = np.concatenate([np.ascontiguousarray(b, np.float64).reshape(-1) for b in B])
+        super().__init__(dims, ranks, A, kruskal_core(ranks, B))
+
+    @property
+    def B(self):
+        out, o = [], 0
+        for J in self.ranks:
+            out.append(self.flatB[o: o + J * self.R].reshape(J, self.R))
+            o += J * self.R
+        return out
+
+    def copy(self):
+        return KruskalModel(self.dims, self.ranks, [a.copy() for a in self.A], [b.copy() for b in self.B])
+
+    def _kargs(self):
+        return (self.N, _ptr(self.dims, _i64p), _ptr(self.ranks, _i32p), _ptr(self.flatA, _f64p), self.R,
+                _ptr(self.flatB, _f64p))
+
+    def W(self, idx, n, r):
+        """W_r of mode n (m x J_n) for the entries ``idx``."""
+        idx = np.ascontiguousarray(idx, np.int32)
+        out = np.empty((idx.shape[1], int(self.ranks[n])), np.float64)
+        _check(lib().orc_kruskal_W(*self._kargs(), idx.shape[1], _ptr(idx, _i32p), n, r, _ptr(out, _f64p)),
+               "orc_kruskal_W")
+        return out
+
+    def column_step(self, idx, x, n, r, gam_B, lam_B):
+        idx = np.ascontiguousarray(idx, np.int32)
+        x = np.ascontiguousarray(x, np.float32)
+        _check(lib().orc_kruskal_column_step(*self._kargs(), idx.shape[1], _ptr(idx, _i32p), _ptr(x, _f32p),
+                                             n, r, gam_B, lam_B), "orc_kruskal_column_step")
+        self.G[:] = kruskal_core(self.ranks, self.B)
+
+    def kruskal_core_step(self, idx, x, gam_B, lam_B):
+        idx = np.ascontiguousarray(idx, np.int32)
+        x = np.ascontiguousarray(x, np.float32)
+        _check(lib().orc_kruskal_core_step(*self._kargs(), _ptr(self.G, _f64p), idx.shape[1], _ptr(idx, _i32p),
+                                           _ptr(x, _f32p), gam_B, lam_B), "orc_kruskal_core_step")
+
+    def step(self, idx, x, gam_A, lam_A, gam_B, lam_B):
+        idx = np.ascontiguousarray(idx, np.int32)
+        x = np.ascontiguousarray(x, np.float32)
+        _check(lib().orc_step_kruskal(*self._kargs(), _ptr(self.G, _f64p), idx.shape[1], _ptr(idx, _i32p),
+                                      _ptr(x, _f32p), gam_A, lam_A, gam_B, lam_B), "orc_step_kruskal")
+
+    def run(self, idx, vals, M, gam_A, lam_A, gam_G, lam_G, perm=None, seed=0, epoch0=0,
+            n_epochs=1, max_batches=-1):
+        """Minibatch SGD epochs with the Kruskal core sub-step (gam_G and
+        lam_G are the paper's gamma_B and lambda_B)."""
+        idx = np.ascontiguousarray(idx, np.int32)
+        vals = np.ascontiguousarray(vals, np.float32)
+        T = idx.shape[1]
+        pp = None
+        if perm is not None:
+            perm = np.ascontiguousarray(perm, np.int64).reshape(-1)
+            assert perm.size == n_epochs * T
+            pp = _ptr(perm, _i64p)
+        done = np.zeros(1, np.int64)
+        _check(lib().orc_run_kruskal(*self._kargs(), _ptr(self.G, _f64p), T, _ptr(idx, _i32p), _ptr(vals, _f32p),
+                                     M, gam_A, lam_A, gam_G, lam_G, pp, ctypes.c_uint64(seed), epoch0, n_epochs,
+                                     max_batches, _ptr(done, _i64p)), "orc_run_kruskal")
         return int(done[0])

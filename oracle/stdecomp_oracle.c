@@ -433,3 +433,247 @@ int orc_run(int N, const int64_t *dims, const int32_t *ranks, double *A, double 
     free(order); free(bidx); free(bx);
     return rc;
 }
+
+/* ======================================================================== */
+/* Kruskal core (Section "Optimization Process for the Core Tensor").        */
+/* The core is approximated by the R_core Kruskal product of the matrices    */
+/* B(n) in R^{J_n x R} (Eq. CP-Decomposition).  B is stored with each B(n)   */
+/* row-major J_n x R, the modes back to back (B(n) starts at                 */
+/* sum_{k<n} J_k * R).                                                       */
+/* READING: the paper requires R_core <= J_n but its rank study uses         */
+/* R_core up to 25 at J_n = 5, so any R >= 1 is accepted here.               */
+/* ======================================================================== */
+
+static void b_offsets(int N, const int32_t *ranks, int R, int64_t *off)
+{
+    int64_t o = 0;
+    for (int n = 0; n < N; n++) {
+        off[n] = o;
+        o += (int64_t)ranks[n] * R;
+    }
+}
+
+/* G[lin(j)] = sum_r prod_k B(k)[j_k, r] (Eq. CP-Decomposition; G flat with
+ * j_0 fastest, as everywhere in this file). */
+int orc_kruskal_core(int N, const int32_t *ranks, int R, const double *B, double *G)
+{
+    int64_t P, boff[ORC_MAXN];
+    int64_t dims1[ORC_MAXN];
+    for (int n = 0; n < N && n < ORC_MAXN; n++) dims1[n] = 1;
+    if (check_model(N, dims1, ranks, &P) || R < 1 || !B || !G) return ORC_EINVAL;
+    b_offsets(N, ranks, R, boff);
+    int j[ORC_MAXN] = {0};
+    for (int64_t lin = 0; lin < P; lin++) {
+        double acc = 0.0;
+        for (int r = 0; r < R; r++) {
+            double t = 1.0;
+            for (int k = 0; k < N; k++) t *= B[boff[k] + (int64_t)j[k] * R + r];
+            acc += t;
+        }
+        G[lin] = acc;
+        odometer_next(N, ranks, j);
+    }
+    return ORC_OK;
+}
+
+/* W_r of mode n for the m samples of a minibatch, built as Algorithm 1's
+ * core loop builds it: the rows of H_Psi in the mode-n vectorisation of Eq.
+ * approximated_core_tensor_optimization (entry j_n + J_n*col holds
+ * prod_k A(k)[i_k, j_k], col the mode-n unfolding column of Definition
+ * "Tensor Unfolding"), the column q_r of the Khatri-Rao product
+ * Q(n) = B(N) (.) ... (.) B(n+1) (.) B(n-1) (.) ... (.) B(1) of Eq. eventual0
+ * (entry col holds prod_{k != n} B(k)[j_k, r]), the block matrix O_r of Eq. Q_r
+ * (the J_n x J_n identity scaled by q_{col,r} in block row col), and
+ * W_r = H_Psi O_r (m x J_n, row-major), all formed explicitly. */
+int orc_kruskal_W(int N, const int64_t *dims, const int32_t *ranks, const double *A, int R,
+                  const double *B, int64_t m, const int32_t *idx, int n, int r, double *W)
+{
+    int64_t P, off[ORC_MAXN], boff[ORC_MAXN], i[ORC_MAXN];
+    if (check_model(N, dims, ranks, &P) || R < 1 || m < 1 || n < 0 || n >= N || r < 0 || r >= R || !W)
+        return ORC_EINVAL;
+    if (check_indices(N, dims, m, idx)) return ORC_EINVAL;
+    factor_offsets(N, dims, ranks, off);
+    b_offsets(N, ranks, R, boff);
+    const int Jn = ranks[n];
+    const int64_t K = P / Jn;
+    double *H = (double *)malloc((size_t)(m * P) * sizeof(double));
+    double *q = (double *)malloc((size_t)K * sizeof(double));
+    double *O = (double *)calloc((size_t)(P * Jn), sizeof(double));
+    if (!H || !q || !O) {
+        free(H); free(q); free(O);
+        return ORC_ENOMEM;
+    }
+    /* H_Psi and q_r, walking the core positions j (j_0 fastest) */
+    int j[ORC_MAXN] = {0};
+    for (int64_t lin = 0; lin < P; lin++) {
+        int64_t col = 0, stride = 1;
+        for (int k = 0; k < N; k++) {
+            if (k == n) continue;
+            col += j[k] * stride;
+            stride *= ranks[k];
+        }
+        const int64_t v = j[n] + (int64_t)Jn * col;
+        for (int64_t s = 0; s < m; s++) {
+            double h = 1.0;
+            for (int k = 0; k < N; k++) {
+                i[k] = idx[k * m + s];
+                h *= row_of(A, off, ranks, k, i[k])[j[k]];
+            }
+            H[s * P + v] = h;
+        }
+        double qv = 1.0;
+        for (int k = 0; k < N; k++)
+            if (k != n) qv *= B[boff[k] + (int64_t)j[k] * R + r];
+        q[col] = qv;
+        odometer_next(N, ranks, j);
+    }
+    /* O_r: block row col is q_{col,r} times the identity */
+    for (int64_t col = 0; col < K; col++)
+        for (int jj = 0; jj < Jn; jj++) O[(jj + Jn * col) * Jn + jj] = q[col];
+    /* W_r = H_Psi O_r */
+    for (int64_t s = 0; s < m; s++)
+        for (int jj = 0; jj < Jn; jj++) {
+            double acc = 0.0;
+            for (int64_t v = 0; v < P; v++) acc += H[s * P + v] * O[v * Jn + jj];
+            W[s * Jn + jj] = acc;
+        }
+    free(H); free(q); free(O);
+    return ORC_OK;
+}
+
+/* The cyclic block steps on the columns rc0..rc1-1 of B(n) (Eq.
+ * eventual_approximated, solved by the averaged SGD of Eq. SGD_core_tensor
+ * with the gradient of Eq. Gradient_core_tensor; Algorithm 1, core loop):
+ * with the W_r of every r computed once for mode n, each column in turn forms
+ *   x_hat = x - sum_{r != rc} W_r b_r          (current columns),
+ *   C = W_rc^T W_rc,  V = -W_rc^T x_hat + C b_rc,
+ *   b_rc <- b_rc - gamma_B * ( V / m + lambda_B b_rc ),
+ * the exact gradient step of (1/2m) ||x - sum_r W_r b_r||^2 + (lambda_B/2)||b_rc||^2
+ * (the 1/M of Eq. Gradient_core_tensor with M = m, the minibatch's size). */
+static int kruskal_columns(int N, const int64_t *dims, const int32_t *ranks, const double *A, int R,
+                           double *B, int64_t m, const int32_t *idx, const float *x, int n, int rc0,
+                           int rc1, double gam_B, double lam_B)
+{
+    int64_t boff[ORC_MAXN];
+    b_offsets(N, ranks, R, boff);
+    const int Jn = ranks[n];
+    double *W = (double *)malloc((size_t)(R * m * Jn) * sizeof(double));
+    double *xh = (double *)malloc((size_t)m * sizeof(double));
+    double *C = (double *)malloc((size_t)(Jn * Jn) * sizeof(double));
+    double *V = (double *)malloc((size_t)Jn * sizeof(double));
+    if (!W || !xh || !C || !V) {
+        free(W); free(xh); free(C); free(V);
+        return ORC_ENOMEM;
+    }
+    int rc = ORC_OK;
+    for (int r = 0; r < R && rc == ORC_OK; r++)
+        rc = orc_kruskal_W(N, dims, ranks, A, R, B, m, idx, n, r, W + (int64_t)r * m * Jn);
+    double *Bn = B + boff[n];
+    for (int c = rc0; c < rc1 && rc == ORC_OK; c++) {
+        const double *Wc = W + (int64_t)c * m * Jn;
+        for (int64_t s = 0; s < m; s++) {
+            double v = (double)x[s];
+            for (int r = 0; r < R; r++) {
+                if (r == c) continue;
+                for (int jj = 0; jj < Jn; jj++) v -= W[((int64_t)r * m + s) * Jn + jj] * Bn[jj * R + r];
+            }
+            xh[s] = v;
+        }
+        for (int a = 0; a < Jn; a++)
+            for (int b = 0; b < Jn; b++) {
+                double acc = 0.0;
+                for (int64_t s = 0; s < m; s++) acc += Wc[s * Jn + a] * Wc[s * Jn + b];
+                C[a * Jn + b] = acc;
+            }
+        for (int a = 0; a < Jn; a++) {
+            double v = 0.0;
+            for (int64_t s = 0; s < m; s++) v -= Wc[s * Jn + a] * xh[s];
+            for (int b = 0; b < Jn; b++) v += C[a * Jn + b] * Bn[b * R + c];
+            V[a] = v;
+        }
+        for (int a = 0; a < Jn; a++)
+            Bn[a * R + c] -= gam_B * (V[a] / (double)m + lam_B * Bn[a * R + c]);
+    }
+    free(W); free(xh); free(C); free(V);
+    return rc;
+}
+
+/* One block step on column rc of B(n) alone (for the gradient pins). */
+int orc_kruskal_column_step(int N, const int64_t *dims, const int32_t *ranks, const double *A, int R,
+                            double *B, int64_t m, const int32_t *idx, const float *x, int n, int rc,
+                            double gam_B, double lam_B)
+{
+    int64_t P;
+    if (check_model(N, dims, ranks, &P) || R < 1 || m < 1 || n < 0 || n >= N || rc < 0 || rc >= R || !B)
+        return ORC_EINVAL;
+    if (check_indices(N, dims, m, idx)) return ORC_EINVAL;
+    return kruskal_columns(N, dims, ranks, A, R, B, m, idx, x, n, rc, rc + 1, gam_B, lam_B);
+}
+
+/* The Kruskal core sub-step of one minibatch (Algorithm 1, core loop and the
+ * forming of the core): for n = 1..N in order, every column of B(n) in
+ * order, each mode's W_r built from the B(k) left by the modes before it;
+ * then G = the Kruskal product of the updated B (Eq. CP-Decomposition). */
+int orc_kruskal_core_step(int N, const int64_t *dims, const int32_t *ranks, const double *A, int R,
+                          double *B, double *G, int64_t m, const int32_t *idx, const float *x,
+                          double gam_B, double lam_B)
+{
+    int64_t P;
+    if (check_model(N, dims, ranks, &P) || R < 1 || m < 1 || !B || !G) return ORC_EINVAL;
+    if (check_indices(N, dims, m, idx)) return ORC_EINVAL;
+    int rc = ORC_OK;
+    for (int n = 0; n < N && rc == ORC_OK; n++)
+        rc = kruskal_columns(N, dims, ranks, A, R, B, m, idx, x, n, 0, R, gam_B, lam_B);
+    if (rc == ORC_OK) rc = orc_kruskal_core(N, ranks, R, B, G);
+    return rc;
+}
+
+/* One minibatch with the Kruskal core: the core sub-step above, then the
+ * factor sub-steps of modes 0..N-1 with the core it formed (Algorithm 1). */
+int orc_step_kruskal(int N, const int64_t *dims, const int32_t *ranks, double *A, int R, double *B,
+                     double *G, int64_t m, const int32_t *idx, const float *x, double gam_A, double lam_A,
+                     double gam_B, double lam_B)
+{
+    int rc = orc_kruskal_core_step(N, dims, ranks, A, R, B, G, m, idx, x, gam_B, lam_B);
+    for (int n = 0; rc == ORC_OK && n < N; n++)
+        rc = orc_mode_step(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A);
+    return rc;
+}
+
+/* Epochs as orc_run, each minibatch by orc_step_kruskal. */
+int orc_run_kruskal(int N, const int64_t *dims, const int32_t *ranks, double *A, int R, double *B, double *G,
+                    int64_t T, const int32_t *idx, const float *vals, int64_t M, double gam_A,
+                    double lam_A, double gam_B, double lam_B, const int64_t *perm, uint64_t seed,
+                    int64_t epoch0, int64_t n_epochs, int64_t max_batches, int64_t *batches_run)
+{
+    int64_t P;
+    if (check_model(N, dims, ranks, &P) || R < 1 || T < 1 || M < 1 || n_epochs < 0) return ORC_EINVAL;
+    if (check_indices(N, dims, T, idx)) return ORC_EINVAL;
+    int64_t *order = (int64_t *)malloc((size_t)T * sizeof(int64_t));
+    int32_t *bidx = (int32_t *)malloc((size_t)(N * M) * sizeof(int32_t));
+    float *bx = (float *)malloc((size_t)M * sizeof(float));
+    if (!order || !bidx || !bx) {
+        free(order); free(bidx); free(bx);
+        return ORC_ENOMEM;
+    }
+    int64_t done = 0;
+    int rc = orc_kruskal_core(N, ranks, R, B, G);
+    for (int64_t e = 0; e < n_epochs && rc == ORC_OK; e++) {
+        if (perm) memcpy(order, perm + e * T, (size_t)T * sizeof(int64_t));
+        else orc_perm(T, seed, epoch0 + e, order);
+        for (int64_t b0 = 0; b0 < T && rc == ORC_OK; b0 += M) {
+            if (max_batches >= 0 && done >= max_batches) break;
+            int64_t m = (T - b0 < M) ? (T - b0) : M;
+            for (int64_t p = 0; p < m; p++) {
+                int64_t t = order[b0 + p];
+                for (int k = 0; k < N; k++) bidx[k * m + p] = idx[k * T + t];
+                bx[p] = vals[t];
+            }
+            rc = orc_step_kruskal(N, dims, ranks, A, R, B, G, m, bidx, bx, gam_A, lam_A, gam_B, lam_B);
+            done++;
+        }
+    }
+    if (batches_run) *batches_run = done;
+    free(order); free(bidx); free(bx);
+    return rc;
+}

@@ -10,6 +10,7 @@ import subprocess
 
 import pytest
 
+import tests.test_oracle_kruskal as kpins
 import tests.test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "stdecomp_oracle.c")
@@ -34,7 +35,22 @@ MUTANTS = {
     "segment_order_desc": ("return pa < pb ? -1 : (pa > pb ? 1 : 0);", "return pa < pb ? 1 : (pa > pb ? -1 : 0);"),
     "modes_before_core": ("int rc = orc_core_step(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G);\n    for (int n = 0; rc == ORC_OK && n < N; n++)\n        rc = orc_mode_step(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A);",
                           "int rc = ORC_OK;\n    for (int n = 0; rc == ORC_OK && n < N; n++)\n        rc = orc_mode_step(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A);\n    if (rc == ORC_OK) rc = orc_core_step(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G);"),
-    "ragged_batch_dropped": ("int64_t m = (T - b0 < M) ? (T - b0) : M;", "int64_t m = M; if (T - b0 < M) break;"),
+    "ragged_batch_dropped": ("int64_t m = (T - b0 < M) ? (T - b0) : M;\n            for (int64_t p = 0; p < m; p++) {\n                int64_t t = order[b0 + p];\n                for (int k = 0; k < N; k++) bidx[k * m + p] = idx[k * T + t];\n                bx[p] = vals[t];\n            }\n            rc = orc_step(",
+                             "int64_t m = M; if (T - b0 < M) break;\n            for (int64_t p = 0; p < m; p++) {\n                int64_t t = order[b0 + p];\n                for (int k = 0; k < N; k++) bidx[k * m + p] = idx[k * T + t];\n                bx[p] = vals[t];\n            }\n            rc = orc_step("),
+    # Kruskal core
+    "kruskal_drops_lambda": ("Bn[a * R + c] -= gam_B * (V[a] / (double)m + lam_B * Bn[a * R + c]);",
+                             "Bn[a * R + c] -= gam_B * (V[a] / (double)m);"),
+    "kruskal_wrong_average": ("Bn[a * R + c] -= gam_B * (V[a] / (double)m + lam_B * Bn[a * R + c]);",
+                              "Bn[a * R + c] -= gam_B * (V[a] / (double)(m + 1) + lam_B * Bn[a * R + c]);"),
+    "kruskal_residual_keeps_own_column": ("                if (r == c) continue;\n", ""),
+    "kruskal_stale_C_term": ("for (int b = 0; b < Jn; b++) v += C[a * Jn + b] * Bn[b * R + c];", ""),
+    "kruskal_q_includes_own_mode": ("if (k != n) qv *= B[boff[k] + (int64_t)j[k] * R + r];",
+                                    "qv *= B[boff[k] + (int64_t)j[k] * R + r];"),
+    "kruskal_vec_order": ("const int64_t v = j[n] + (int64_t)Jn * col;", "const int64_t v = col + K * j[n];"),
+    "kruskal_modes_reversed": ("for (int n = 0; n < N && rc == ORC_OK; n++)\n        rc = kruskal_columns(",
+                               "for (int n = N - 1; n >= 0 && rc == ORC_OK; n--)\n        rc = kruskal_columns("),
+    "kruskal_core_not_formed": ("    if (rc == ORC_OK) rc = orc_kruskal_core(N, ranks, R, B, G);\n    return rc;\n}",
+                                "    return rc;\n}"),
 }
 
 
@@ -51,6 +67,12 @@ def _pin_calls():
         (pins.test_step_order_core_then_modes, {}),
         (pins.test_matrix_factorisation_exact, {}),
         (pins.test_run_uses_sampler_and_ragged_last_batch, {}),
+        (kpins.test_kruskal_core_is_sum_of_outer_products, {"ranks": (2, 3, 4), "R": 2}),
+        (kpins.test_W_closed_form_and_prediction, {"dims": (5, 4, 6), "ranks": (2, 3, 2), "R": 3}),
+        (kpins.test_column_step_is_gradient, {"dims": (5, 4, 6), "ranks": (2, 3, 2), "R": 3, "n": 0, "r": 1}),
+        (kpins.test_core_step_is_cyclic_over_modes_then_columns, {}),
+        (kpins.test_matrix_factorisation_exact_kruskal, {}),
+        (kpins.test_kruskal_step_then_factor_steps, {}),
     ]
 
 
