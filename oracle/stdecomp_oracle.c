@@ -126,7 +126,7 @@ int orc_segments(int64_t m, const int32_t *rows, int32_t *sigma,
         return ORC_EINVAL;
     for (int64_t p = 0; p < m; p++) sigma[p] = (int32_t)p;
     g_sort_rows = rows;
-    qsort(sigma, (size_t)m, sizeof(int32_t), cmp_row_pos);
+    if (m > 0) qsort(sigma, (size_t)m, sizeof(int32_t), cmp_row_pos);
     int32_t d = 0;
     for (int64_t q = 0; q < m; q++) {
         if (q == 0 || rows[sigma[q]] != rows[sigma[q - 1]]) {
@@ -136,7 +136,7 @@ int orc_segments(int64_t m, const int32_t *rows, int32_t *sigma,
         }
     }
     if (m > 0) seg_off[d] = (int32_t)m;
-    else seg_off[0] = 0;
+    else if (seg_off) seg_off[0] = 0;
     *nseg = d;
     return ORC_OK;
 }
