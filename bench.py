@@ -1,13 +1,18 @@
 """Throughput of the SGD_Tucker minibatch update on one MI355X.
 
-Workload: the Netflix-shaped rating tensor -- 480000 x 18000 x 2000, 100M
-nonzeros with Zipf(1.1) indices per mode and ratings 1..5, 10% held out --
-with core ranks J = (10, 10, 10) and minibatches of M = 4096 (synthetic data,
-random initial parameters).  One step = one epoch over the ~90M training
-entries (sampler, row-set sort, minibatch chain) followed by the held-out
-RMSE.  Prints one JSON line.
+Default workload (the precision comparison the metric is quoted on): a
+4-order tensor 100000 x 100000 x 1000 x 100 with 200M nonzeros, power-law
+(Zipf 1.2) indices on modes 1-2 and uniform indices on modes 3-4, values from
+a planted rank-(8,8,8,8) Tucker model plus N(0, 0.05^2) noise, 10% held out;
+core ranks J = (8,8,8,8), minibatches of M = 8192 (synthetic data, random
+initial parameters).  One step = one epoch over the 180M training entries
+(sampler, row-set sort, minibatch chain) followed by the held-out RMSE.  The
+FP32 path is the headline value; the BF16 path (BF16 operands, FP32 masters
+and accumulation) runs the same steps from the same initial parameters and is
+reported beside it, each with its held-out RMSE gap to the FP64 oracle on the
+first minibatches of epoch 0.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--dtype f32|bf16]
+    python bench.py [--steps K] [--warmup W] [--config c3|c2|c4|c5|ranks]
 """
 import argparse
 import json
@@ -17,6 +22,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+METRIC = "nonzero-updates/sec/GPU at fixed held-out RMSE (FP32 vs BF16); serve p50/p99"
 
 PEAK = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
@@ -35,21 +42,23 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
-    ap.add_argument("--nnz", type=int, default=100_000_000)
+    ap.add_argument("--nnz", type=int, default=0, help="entries before the held-out split (0: the config's)")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-batches", type=int, default=60,
-                    help="minibatches of the CPU oracle baseline (0: skip)")
+    ap.add_argument("--cpu-batches", type=int, default=-1,
+                    help="minibatches of the CPU oracle baseline (0: skip; -1: the config's default, c3: 48, c2: 60)")
+    ap.add_argument("--prefix", type=int, default=200,
+                    help="(c3) minibatches of epoch 0 on which each dtype is compared with the FP64 oracle "
+                         "(0: skip; the oracle runs them in a thread beside the GPU steps)")
     ap.add_argument("--traffic-json", default=None,
-                    help="counter record of the chain (default: profiles/chain_traffic.json for FP32, "
-                         "profiles/chain_traffic_bf16.json for BF16)")
+                    help="(c2) counter record of the chain (default: profiles/chain_traffic_ratings_zipf[_bf16].json)")
     ap.add_argument("--duration", type=float, default=10.0, help="(c5) seconds of job arrivals")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "ranks"],
-                    help="c2: Netflix-shaped ratings (default); c3: 4-order planted power-law tensor, FP32 vs BF16; "
+    ap.add_argument("--config", default="c3", choices=["c2", "c3", "c4", "c5", "ranks"],
+                    help="c3 (default): 4-order planted power-law tensor, FP32 vs BF16; c2: Netflix-shaped ratings; "
                          "c4: 64 independent planted tensors, batched launches vs one model at a time; "
                          "c5: serving loop (Poisson jobs and queries), p50/p99 latency; "
                          "ranks: core-rank sweep J = 4..24 on a ratings tensor")
-    ap.add_argument("--epochs", type=int, default=5, help="(c3) epochs per precision")
+    ap.add_argument("--dtypes", default="f32,bf16", help="(c3) precisions to run, the first is the headline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -75,6 +84,9 @@ def main():
     if args.config == "c3":
         run_c3(args)
         return
+    if args.config == "c2":
+        run_c2(args)
+        return
     if args.config == "c4":
         run_c4(args)
         return
@@ -85,6 +97,11 @@ def main():
         run_ranks(args)
         return
 
+
+def run_c2(args):
+    """Netflix-shaped ratings: 480000 x 18000 x 2000, 100M entries (Zipf 1.1
+    per mode, ratings 1..5, 10% held out), J = (10,10,10), M = 4096,
+    lr = lambda = 0.01; step = one epoch + held-out RMSE."""
     import numpy as np
     import torch
 
@@ -93,7 +110,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t = time.time()
-    wl = synth.ratings_zipf(nnz=args.nnz)
+    wl = synth.ratings_zipf(nnz=args.nnz or 100_000_000)
     log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
     M = args.batch
     lr = lam = 0.01
@@ -131,31 +148,18 @@ def main():
 
     # roofline of the dominant kernel (the minibatch chain), from the
     # library's HIP events on its own stream
-    launches = acc["chain_launches"]
-    avg_launch = acc["chain_seconds"] / launches
-    flops_per_launch = acc["flops_alg"] / launches
-    achieved = flops_per_launch / avg_launch / 1e12
-    peak = PEAK["bf16_TFs"] if args.dtype == "bf16" else PEAK["fp32_TFs"]
-    traffic = None
-    tpath = args.traffic_json or os.path.join(
-        ROOT, "profiles", "chain_traffic.json" if args.dtype == "f32" else "chain_traffic_%s.json" % args.dtype)
-    if os.path.exists(tpath):
-        tj = json.load(open(tpath))
-        if tj.get("kernel_source_hash") == kernel_source_hash() and tj.get("dtype") == args.dtype:
-            traffic = tj.get("bytes_per_launch")
-    roofline = {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6), "traffic": traffic,
-                "kernel": "k_chain", "avg_launch_ms": round(avg_launch * 1e3, 3),
-                "hbm_alg_GBs": round(acc["bytes_alg"] / acc["chain_seconds"] / 1e9, 2),
-                "latency_bound": latency_bound(h, M, len(wl.dims), updates / acc["chain_seconds"])}
+    tpath = args.traffic_json or traffic_path("ratings_zipf", args.dtype)
+    roofline = chain_roofline(acc, args.dtype, stored_traffic(tpath, args.dtype, wl.nnz, M, info),
+                              latency_bound(h, M, len(wl.dims), updates / acc["chain_seconds"]))
 
     cpu = None
-    if args.cpu_batches > 0:
-        cpu = cpu_baseline(h, wl, A0, G0, M, lr, lam, args.cpu_batches)
+    cpu_batches = 60 if args.cpu_batches < 0 else args.cpu_batches
+    if cpu_batches > 0:
+        cpu = cpu_baseline(h, wl, A0, G0, M, lr, lam, cpu_batches)
     h.close()
 
     out = {
-        "metric": "nonzero-updates/sec/GPU at fixed held-out RMSE",
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "nonzero-updates/s",
         "n_gpus": 1,
@@ -179,114 +183,193 @@ def main():
 
 
 def run_c3(args):
-    """4-order planted power-law tensor 100000x100000x1000x100, 200M entries
-    (Zipf 1.2 on modes 1-2, uniform on 3-4), planted rank (8,8,8,8) plus
-    N(0, 0.05^2) noise, 10% held out; J = (8,8,8,8), M = 8192, lr = 0.05,
-    lambda = 1e-4 (at lr = lambda = 0.01, or lambda = 1e-3, the model decays
-    to the zero saddle and stays there; at lr = 0.1 it diverges in the first
-    epoch), ``--epochs`` epochs in FP32 and in BF16 from the same initial
-    parameters.  Precision: the FP64 oracle, the FP32 chain and the BF16 chain
-    run the same first 200 minibatches of epoch 0 and their held-out RMSE is
-    compared on a 200,000-entry sample of the held-out set."""
+    """The precision comparison (default): 4-order planted power-law tensor
+    100000x100000x1000x100, 200M entries (Zipf 1.2 on modes 1-2, uniform on
+    3-4), planted rank (8,8,8,8) plus N(0, 0.05^2) noise, 10% held out;
+    J = (8,8,8,8), M = 8192, lr = 0.05, lambda = 1e-4 (at lr = lambda = 0.01,
+    or lambda = 1e-3, the model decays to the zero saddle and stays there; at
+    lr = 0.1 it diverges in the first epoch).  Each dtype runs W warm-up and
+    K timed steps (one epoch + held-out RMSE each) from the same initial
+    parameters.  Before that, each runs the first ``--prefix`` minibatches of
+    epoch 0, and the FP64 oracle runs the same minibatches from the same
+    parameters in a thread beside the GPU work: the parameter and held-out
+    RMSE gaps of each dtype to the oracle are reported, and the oracle's
+    first ``--cpu-batches`` minibatches are its timed baseline."""
+    import threading
+
     import numpy as np
     import torch
-    from oracle import oracle
     from paper_2012_03550_amd import binding, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    nnz = args.nnz if args.nnz != 100_000_000 else 200_000_000
+    nnz = args.nnz or 200_000_000
     t = time.time()
     wl = synth.planted_powerlaw(nnz=nnz, device="cuda")
     log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
-    M, lr, lam, prefix, sample = 8192, 0.05, 1e-4, 200, 200_000
+    M, lr, lam, sample = 8192, 0.05, 1e-4, 200_000
+    seed_s, seed_i = 3003, 2003
+    prefix = max(0, args.prefix)
+    cpu_batches = 48 if args.cpu_batches < 0 else args.cpu_batches
+    cpu_batches = min(cpu_batches, prefix) if prefix else cpu_batches
+    dtypes = [d for d in args.dtypes.split(",") if d]
     test_idx = torch.from_numpy(wl.test_idx).cuda()
     test_vals = torch.from_numpy(wl.test_vals).cuda()
     s_idx = np.ascontiguousarray(wl.test_idx[:, :sample])
     s_vals = np.ascontiguousarray(wl.test_vals[:sample])
-    res = {}
+    res, orc = {}, {}
     A0 = G0 = None
-    for dtype in ("f32", "bf16"):
+    worker = None
+    for dtype in dtypes:
         h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
-                             lam_factor=lam, lam_core=lam, seed_sample=3003, seed_init=2003, dtype=dtype)
+                             lam_factor=lam, lam_core=lam, seed_sample=seed_s, seed_init=seed_i, dtype=dtype)
         if A0 is None:
             A0, G0 = h.get_params()
-        h.run_minibatches(0, 0, prefix)
-        prefix_rmse = h.loss(s_idx, s_vals)["rmse"]
+            if prefix > 0 or cpu_batches > 0:
+                worker = threading.Thread(target=oracle_prefix, daemon=True,
+                                          args=(wl, A0, G0, M, lr, lam, seed_s, max(prefix, cpu_batches),
+                                                cpu_batches, s_idx, s_vals, orc))
+                worker.start()
+        info = h.info()
+        log("c3 %s chain" % dtype, info)
+        r = {"chain_workgroups": info["workgroups"], "chain_chunk": info["chunk"]}
+        if prefix > 0:
+            h.run_minibatches(0, 0, prefix)
+            r["prefix_params"] = h.get_params()
+            r["prefix_heldout_rmse_sample"] = h.loss(s_idx, s_vals)["rmse"]
         h.set_params(A0, G0)
         A1, G1 = h.get_params()
         if not (all(np.array_equal(a, b) for a, b in zip(A0, A1)) and np.array_equal(G0, G1)):
             raise RuntimeError("c3 %s: parameters read back after set_params differ from those set" % dtype)
         h.set_epoch(0)
+        for w in range(args.warmup):
+            st = h.epoch(1)
+            ls = h.loss(test_idx, test_vals)
+            log("c3 %s warmup epoch %d: %.3fs device, held-out RMSE %.5f" % (dtype, w, st["device_seconds"],
+                                                                           ls["rmse"]))
+        acc, rmse = None, []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dev = 0.0
-        chain_s = 0.0
-        launches = 0
-        bytes_alg = 0.0
-        rmse = []
-        done = 0
-        for e in range(args.epochs):
-            try:
-                st = h.epoch(1)
-            except binding.StdecompError as ex:
-                log("c3 %s epoch %d: %s" % (dtype, e, ex))
-                rmse.append("diverged")
-                break
-            done += 1
-            dev += st["device_seconds"]
-            chain_s += st["chain_seconds"]
-            launches += st["chain_launches"]
-            bytes_alg += st["bytes_alg"]
-            rmse.append(round(h.loss(test_idx, test_vals)["rmse"], 6))
-            log("c3 %s epoch %d: chain %.3fs held-out RMSE %.5f" % (dtype, e, st["chain_seconds"], rmse[-1]))
+        for k in range(args.steps):
+            st = h.epoch(1)
+            rmse.append(h.loss(test_idx, test_vals)["rmse"])
+            acc = dict(st) if acc is None else {key: acc[key] + st[key] for key in st}
+            log("c3 %s step %d: chain %.3fs schedule %.4fs held-out RMSE %.5f" % (
+                dtype, k, st["chain_seconds"], st["schedule_seconds"], rmse[-1]))
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        info = h.info()
-        lat = latency_bound(h, M, len(wl.dims), wl.nnz * done / chain_s) if done else None
+        elapsed = time.perf_counter() - t0
+        updates = acc["updates"]
+        lat = latency_bound(h, M, len(wl.dims), updates / acc["chain_seconds"])
         h.close()
-        flops = (2 * len(wl.dims) + 4) * int(np.prod(wl.ranks))  # per nonzero-update
-        peak = 157.3 if dtype == "f32" else 2500.0
-        ach = wl.nnz * done * flops / chain_s / 1e12 if done else None
-        res[dtype] = {"updates_per_s": round(wl.nnz * done / wall, 1) if done else None, "device_updates_per_s":
-                      round(wl.nnz * done / dev, 1) if done else None,
-                      "roofline": {"bound": "mfma", "achieved": round(ach, 4) if done else None, "peak": peak,
-                                   "unit": "TFLOP/s", "frac": round(ach / peak, 6) if done else None,
-                                   "traffic": c3_traffic(dtype, wl.nnz), "kernel": "k_chain",
-                                   "chain_seconds": round(chain_s, 4), "chain_launches": launches,
-                                   "avg_launch_ms": round(chain_s / launches * 1e3, 3) if launches else None,
-                                   "alg_bytes_per_launch": int(bytes_alg / launches) if launches else None,
-                                   "latency_bound": lat},
-                      "heldout_rmse_per_epoch": rmse,
-                      "prefix_heldout_rmse_sample": prefix_rmse, "chain_workgroups": info["workgroups"],
-                      "chain_chunk": info["chunk"]}
-    precision = cpu = None
-    if args.cpu_batches > 0:  # (--cpu-batches 0: no oracle, for profiling runs)
-        oracle.build()
-        ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
-        log("oracle: running %d minibatches of epoch 0" % prefix)
-        t = time.perf_counter()
-        ref.run(wl.train_idx, wl.train_vals, M, lr, lam, lr, lam, seed=3003, epoch0=0, n_epochs=1, max_batches=prefix)
-        dt = time.perf_counter() - t
-        orc = ref.loss(s_idx, s_vals)["rmse"]
-        log("oracle: %d minibatches in %.1fs, sample held-out RMSE %.6f" % (prefix, dt, orc))
-        precision = {"prefix_minibatches": prefix, "heldout_sample": sample, "rmse_oracle_f64": orc,
-                     "rmse_f32": res["f32"]["prefix_heldout_rmse_sample"],
-                     "rmse_bf16": res["bf16"]["prefix_heldout_rmse_sample"],
-                     "f32_rel_gap": (res["f32"]["prefix_heldout_rmse_sample"] - orc) / orc,
-                     "bf16_rel_gap": (res["bf16"]["prefix_heldout_rmse_sample"] - orc) / orc}
-        cpu = dict({"value": round(prefix * M / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
-                    "sample": "first %d minibatches of epoch 0, FP64 C, one thread" % prefix}, **host_cpu())
-    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": res["f32"]["updates_per_s"],
-           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.epochs, "warmup": 0, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        r.update({"value": round(updates / elapsed, 1), "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+                  "device_updates_per_s": round(updates / acc["device_seconds"], 1),
+                  "heldout_rmse_per_step": [round(x, 6) for x in rmse],
+                  "roofline": chain_roofline(acc, dtype, stored_traffic(traffic_path("planted_powerlaw", dtype),
+                                                                         dtype, wl.nnz, M, info), lat)})
+        res[dtype] = r
+    if worker is not None:
+        log("waiting for the oracle")
+        worker.join()
+    head = res[dtypes[0]]
+    precision = None
+    if prefix > 0 and "A" in orc:
+        precision = {"prefix_minibatches": prefix, "heldout_sample": sample,
+                     "rmse_oracle_f64": round(orc["rmse"], 9)}
+        for dtype in dtypes:
+            Ag, Gg = res[dtype].pop("prefix_params")
+            rg = res[dtype].pop("prefix_heldout_rmse_sample")
+            errs = [rel_err(Ag[n], orc["A"][n]) for n in range(len(wl.dims))] + [rel_err(Gg, orc["G"])]
+            precision[dtype] = {"rmse": round(rg, 9), "rmse_rel_gap": (rg - orc["rmse"]) / orc["rmse"],
+                                "params_max_rel_err": max(errs)}
+    else:
+        for dtype in dtypes:
+            res[dtype].pop("prefix_params", None)
+            res[dtype].pop("prefix_heldout_rmse_sample", None)
+    cpu = None
+    if cpu_batches > 0 and "seconds" in orc:
+        cpu = dict({"value": round(cpu_batches * M / orc["seconds"], 1), "unit": "nonzero-updates/s", "cores": 1,
+                    "kind": "oracle",
+                    "sample": "first %d minibatches (%d updates) of epoch 0 from the same initial parameters, FP64 C, "
+                              "one thread" % (cpu_batches, cpu_batches * M)}, **host_cpu())
+    if len(dtypes) > 1 and head["value"]:
+        for dtype in dtypes[1:]:
+            res[dtype]["speedup_vs_%s" % dtypes[0]] = round(res[dtype]["value"] / head["value"], 4)
+    out = {"metric": METRIC, "value": head["value"],
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtypes[0], "data": "synthetic",
            "config": {"workload": "planted_powerlaw 100000x100000x1000x100, %d entries (Zipf 1.2 on modes 1-2, "
                                   "uniform on 3-4), planted rank 8^4 + N(0,0.05^2), 10%% held out; J=(8,8,8,8), "
                                   "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
-                      "train_entries": int(wl.nnz), "batch": M},
-           "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"], "precision": precision,
-           "cpu_baseline": cpu}
+                      "train_entries": int(wl.nnz), "batch": M, "chain_workgroups": head["chain_workgroups"],
+                      "chain_chunk": head["chain_chunk"]},
+           "heldout_rmse": head["heldout_rmse_per_step"][-1] if head["heldout_rmse_per_step"] else None,
+           "roofline": head["roofline"], "precision": precision, "cpu_baseline": cpu}
+    for dtype in dtypes[1:]:
+        out[dtype] = res[dtype]
     print(json.dumps(out), flush=True)
+
+
+def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out):
+    """The FP64 oracle on minibatches [0, nb) of epoch 0 from (A0, G0): the
+    entries of those minibatches are taken in the oracle's own epoch order
+    and run as a tensor of nb * M entries in identity order (the same
+    minibatches); the first nb_timed are timed apart.  Fills out['A'],
+    out['G'], out['rmse'] (held-out sample) and out['seconds']."""
+    import numpy as np
+    from oracle import oracle
+    oracle.build()
+    T = wl.nnz
+    order = oracle.perm(T, seed, 0)[: min(T, nb * M)]
+    idx = np.ascontiguousarray(wl.train_idx[:, order])
+    vals = np.ascontiguousarray(wl.train_vals[order])
+    del order
+    ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    cut = min(idx.shape[1], nb_timed * M)
+    log("oracle: running %d minibatches of epoch 0 (%d timed)" % (nb, nb_timed))
+    t = time.perf_counter()
+    if cut > 0:
+        ref.run(idx[:, :cut], vals[:cut], M, lr, lam, lr, lam, perm=np.arange(cut, dtype=np.int64))
+    out["seconds"] = time.perf_counter() - t
+    if idx.shape[1] > cut:
+        rest = idx.shape[1] - cut
+        ref.run(idx[:, cut:], vals[cut:], M, lr, lam, lr, lam, perm=np.arange(rest, dtype=np.int64))
+    out["rmse"] = ref.loss(s_idx, s_vals)["rmse"]
+    out["A"] = [a.copy() for a in ref.A]
+    out["G"] = ref.G.copy()
+    log("oracle: %d minibatches in %.1fs (first %d in %.1fs), sample held-out RMSE %.6f" % (
+        nb, time.perf_counter() - t, nb_timed, out["seconds"], out["rmse"]))
+
+
+def rel_err(a, ref):
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    n = np.linalg.norm(ref.ravel())
+    d = np.linalg.norm((a - ref).ravel())
+    return float(d / n) if n > 0 else float(d)
+
+
+def chain_roofline(acc, dtype, traffic, lat):
+    """Roofline object of the minibatch chain from the library's HIP-event
+    times on its own stream: MFMA (the contractions) against the dtype's dense
+    peak, and HBM, algorithmic bytes and counter traffic per launch against
+    the 8 TB/s peak."""
+    launches = acc["chain_launches"]
+    avg = acc["chain_seconds"] / launches
+    flops = acc["flops_alg"] / launches
+    alg = acc["bytes_alg"] / launches
+    peak = PEAK["bf16_TFs"] if dtype == "bf16" else PEAK["fp32_TFs"]
+    ach = flops / avg / 1e12
+    hbm = {"alg_bytes_per_launch": int(alg), "alg_GBs": round(alg / avg / 1e9, 3),
+           "alg_frac": round(alg / avg / 1e9 / PEAK["hbm_GBs"], 6), "peak_GBs": PEAK["hbm_GBs"]}
+    if traffic:
+        hbm.update({"traffic_bytes_per_launch": int(traffic), "traffic_GBs": round(traffic / avg / 1e9, 3),
+                    "traffic_frac": round(traffic / avg / 1e9 / PEAK["hbm_GBs"], 6),
+                    "traffic_over_alg": round(traffic / alg, 3)})
+    return {"bound": "mfma", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 6),
+            "traffic": int(traffic) if traffic else None, "kernel": "k_chain", "launches": launches,
+            "avg_launch_ms": round(avg * 1e3, 3), "hbm": hbm, "latency_bound": lat}
 
 
 def run_c4(args):
@@ -349,7 +432,7 @@ def run_c4(args):
         ref.run(w.train_idx, w.train_vals, M, lr, lam, lr, lam, seed=3004 + k, epoch0=0, n_epochs=1)
         upd += w.nnz
     dt = time.perf_counter() - t
-    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": res["f32"]["updates_per_s"],
+    out = {"metric": METRIC, "value": res["f32"]["updates_per_s"],
            "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "64 planted three-mode tensors, mode sizes 10^U(3,6), 10^U(4,7) entries, J from "
@@ -433,7 +516,7 @@ def run_c5(args):
             break
     wall = clock()
     jl = [j.finished - j.arrival for j in srv.done]
-    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": round(srv.updates / wall, 1),
+    out = {"metric": METRIC, "value": round(srv.updates / wall, 1),
            "unit": "nonzero-updates/s", "n_gpus": 1, "steps": rounds, "warmup": 0, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": "serving: Poisson jobs 20/s for %gs (order 3-4, 10^U(4,6) entries, J in {4,8,16}, "
@@ -493,7 +576,7 @@ def run_ranks(args):
         log("J=%d: %.3e updates/s, %.1f us per minibatch, held-out RMSE %.5f" % (J, rows[-1]["updates_per_s"],
                                                                              per_mb * 1e6, rmse))
     best = max((r["updates_per_s"] for r in rows if r.get("fits")), default=None)
-    out = {"metric": "nonzero-updates/sec/GPU at fixed held-out RMSE", "value": rows[3].get("updates_per_s") if len(rows) > 3 else best,
+    out = {"metric": METRIC, "value": rows[3].get("updates_per_s") if len(rows) > 3 else best,
            "unit": "nonzero-updates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": "ratings_zipf 480000x18000x2000 at 20M entries, equal ranks J = 4..24, M=4096; "
@@ -524,16 +607,21 @@ def host_cpu():
     return {"host_cpu": model, "host_threads": os.cpu_count()}
 
 
-def c3_traffic(dtype, train_entries):
-    """HBM bytes per chain launch of the config-3 epoch (FETCH_SIZE and
-    WRITE_SIZE scaled by the copy-kernel factors), if the stored counter record
-    was taken on this kernel source, dtype and training-set size; else None."""
-    path = os.path.join(ROOT, "profiles", "chain_traffic_planted_powerlaw%s.json" % ("" if dtype == "f32" else "_bf16"))
+def traffic_path(workload, dtype):
+    return os.path.join(ROOT, "profiles", "chain_traffic_%s%s.json" % (workload, "" if dtype == "f32" else "_" + dtype))
+
+
+def stored_traffic(path, dtype, train_entries, batch, info):
+    """HBM bytes per chain launch (FETCH_SIZE and WRITE_SIZE scaled by the
+    copy-kernel factors) from a stored counter record, if it was taken on this
+    kernel source, dtype, training-set size, minibatch size and chain geometry
+    (workgroups, chunk); else None."""
     if not os.path.exists(path):
         return None
     tj = json.load(open(path))
-    if (tj.get("kernel_source_hash") != kernel_source_hash() or tj.get("dtype") != dtype
-            or tj.get("train_entries") != train_entries):
+    want = {"kernel_source_hash": kernel_source_hash(), "dtype": dtype, "train_entries": int(train_entries),
+            "batch": int(batch), "workgroups": int(info["workgroups"]), "chunk": int(info["chunk"])}
+    if any(tj.get(k) != v for k, v in want.items()):
         return None
     return tj.get("bytes_per_launch")
 

@@ -26,6 +26,7 @@
 #ifndef STDECOMP_H
 #define STDECOMP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -48,6 +49,15 @@ extern "C" {
 
 typedef struct stdecomp_handle stdecomp_handle;
 
+/* Caller-supplied device memory (e.g. a framework's caching allocator).
+ * alloc returns a device pointer to at least `bytes` bytes, aligned to 256
+ * bytes, that work on `stream` (the handle's hipStream_t) may use, or NULL on
+ * failure; free releases a pointer alloc returned, after all work the handle
+ * queued on `stream` has finished.  Both are called from the thread that calls
+ * the library, with `ctx` as given in the options. */
+typedef void* (*stdecomp_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*stdecomp_free_fn)(void* ctx, void* ptr, void* stream);
+
 /* The tensor (Section "Notation and Preliminaries"). */
 typedef struct {
   int32_t order;        /* N, 2 <= N <= 8 */
@@ -69,14 +79,30 @@ typedef struct {
   uint64_t seed_init;     /* seed of the host initialiser */
   int32_t init_kind;      /* STD_INIT_* */
   int32_t dtype;          /* STD_DTYPE_* */
-  int32_t r_core;         /* 0: dense core (the only value accepted) */
+  int32_t r_core;         /* 0: dense core G updated by SGD on Eq. approximated_core_tensor_optimization.
+                             1..64: the paper's Kruskal core, G = sum_r b(1)_r o ... o b(N)_r
+                             (Eq. CP-Decomposition) with B(n) in R^{J_n x R}: each minibatch
+                             takes the column steps of Algorithm 1's core loop on B (Eqs.
+                             eventual_approximated, Gradient_core_tensor; lr_core and
+                             lambda_core are gamma_B and lambda_B) and then the factor steps
+                             with the core they form.  R J_max + 1 columns of a Gram matrix
+                             must fit one workgroup's LDS (STD_E_INVAL otherwise) */
   int32_t inputs_on_device; /* 1: problem.idx / problem.vals are device pointers */
   void* stream;           /* hipStream_t to run on, or NULL for a private stream */
   int32_t chain_chunk;    /* entries per workgroup per sub-step; 0: automatic, about M/32,
                              halved while chunk * prod(J) > 2^18 (three modes; 2^19
                              otherwise) or the rows of one
                              workgroup exceed its LDS */
-  int32_t reserved[15];   /* must be zero */
+  stdecomp_alloc_fn dev_alloc; /* NULL: hipMalloc.  Otherwise every device buffer the handle
+                                  holds or a call of it needs comes from dev_alloc and goes
+                                  back through dev_free (both must be given); a NULL return
+                                  makes the call fail with STD_E_NOMEM, releasing what it
+                                  had allocated */
+  stdecomp_free_fn dev_free;
+  void* alloc_ctx;             /* passed to dev_alloc / dev_free */
+  int32_t report_train_rmse;   /* 1: stdecomp_epoch also evaluates the RMSE over Omega after
+                                  its last epoch (one pass of the loss kernel over T entries) */
+  int32_t reserved[11];        /* must be zero */
 } stdecomp_options;
 
 typedef struct {
@@ -89,6 +115,8 @@ typedef struct {
   int64_t chain_launches;  /* chain kernel launches */
   double bytes_alg;        /* algorithmic bytes of the chain (COO read + rows read/written + core) */
   double flops_alg;        /* algorithmic flops of the chain, (2N+4) * prod(J) per update */
+  double train_rmse;       /* RMSE over Omega after the last epoch (Section "Experimental
+                              Settings"), FP64 sums; NaN unless options.report_train_rmse */
 } stdecomp_epoch_stats;
 
 typedef struct {
@@ -153,6 +181,15 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
 int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G);
 int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G);
 
+/* Kruskal core (options.r_core = R > 0): copy the FP32 masters of B(n)
+ * (B[n] points to J_n x R row-major floats) out of / into the handle.
+ * set_kruskal also sets the core to their Kruskal product (Eq.
+ * CP-Decomposition, computed on the host in FP64 and rounded to FP32), so
+ * that predictions and losses before the next epoch use it.  STD_E_STATE for
+ * a dense-core handle, STD_E_INVAL for NULL pointers. */
+int stdecomp_get_kruskal(stdecomp_handle* h, float* const* B);
+int stdecomp_set_kruskal(stdecomp_handle* h, const float* const* B);
+
 /* Epoch counter: the next stdecomp_epoch runs epoch e.  Resuming from saved
  * parameters at epoch e reproduces the uninterrupted run bit for bit. */
 int stdecomp_set_epoch(stdecomp_handle* h, int64_t e);
@@ -186,8 +223,15 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
  * reps or a null output, STD_E_DEVICE if a workgroup gave up waiting. */
 int stdecomp_debug_barrier(stdecomp_handle* h, int32_t reps, double* us_per_barrier);
 
-/* The GPU sampler alone: out[q] = pi_e(q) for q in [0, T), host output. */
-int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out);
+/* The GPU sampler alone: out[q] = pi_e(q) for q in [0, T) (the epoch order of
+ * Section "Stochastic Optimization", minibatch b = positions [bM, (b+1)M)).
+ * out: T int64 values, device memory when out_on_device (written by a kernel
+ * on `stream`, nothing allocated), else host memory (a temporary device
+ * buffer is allocated and freed).  stream: a hipStream_t or NULL (the null
+ * stream).  Returns after the work has finished.  STD_E_INVAL for T < 1,
+ * epoch < 0 or out == NULL, STD_E_NOMEM, STD_E_DEVICE. */
+int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, int32_t out_on_device,
+                          void* stream);
 
 int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out);
 

@@ -5,8 +5,10 @@ library's HIP kernels.  Host arrays are numpy; device arrays may be torch
 tensors on a HIP device (their data pointers are passed with on_device=1).
 The binding raises if the library has not been built -- there is no fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -27,19 +29,25 @@ class Problem(ctypes.Structure):
                 ("idx", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int64), ("lr_factor", ctypes.c_float), ("lr_core", ctypes.c_float),
                 ("lambda_factor", ctypes.c_float), ("lambda_core", ctypes.c_float),
                 ("seed_sample", ctypes.c_uint64), ("seed_init", ctypes.c_uint64), ("init_kind", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("r_core", ctypes.c_int32), ("inputs_on_device", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("chain_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 15)]
+                ("stream", ctypes.c_void_p), ("chain_chunk", ctypes.c_int32), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p), ("report_train_rmse", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 11)]
 
 
 class EpochStats(ctypes.Structure):
     _fields_ = [("epochs_run", ctypes.c_int64), ("updates", ctypes.c_int64), ("minibatches", ctypes.c_int64),
                 ("device_seconds", ctypes.c_double), ("schedule_seconds", ctypes.c_double),
                 ("chain_seconds", ctypes.c_double), ("chain_launches", ctypes.c_int64),
-                ("bytes_alg", ctypes.c_double), ("flops_alg", ctypes.c_double)]
+                ("bytes_alg", ctypes.c_double), ("flops_alg", ctypes.c_double), ("train_rmse", ctypes.c_double)]
 
 
 class LossOut(ctypes.Structure):
@@ -66,9 +74,12 @@ SIGNATURES = {
     "stdecomp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "stdecomp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "stdecomp_set_epoch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "stdecomp_get_kruskal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "stdecomp_set_kruskal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "stdecomp_debug_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p,
                                                _i32p, _i32p, _i32p, _i32p, _i32p]),
-    "stdecomp_sample_order": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, _i64p]),
+    "stdecomp_sample_order": (ctypes.c_int, [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_void_p]),
     "stdecomp_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(InfoOut)]),
     "stdecomp_debug_barrier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "stdecomp_epoch_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
@@ -91,12 +102,28 @@ def load():
         # loaded: two runtimes in one process do not share the device
         import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
+        # registered after torch's own exit hooks, so it runs before them
+        atexit.register(_close_live_handles)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
         _lib = L
     return _lib
+
+
+# Handles still open.  They are released by an exit hook, before the
+# interpreter tears down its modules (and with them torch's HIP runtime state),
+# instead of by __del__ during that teardown in an unspecified order.
+_live = weakref.WeakSet()
+
+
+def _close_live_handles():
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
 
 
 class StdecompError(RuntimeError):
@@ -121,6 +148,46 @@ def _dev_coo(idx, vals=None):
     return idx if vals is None else (idx, vals)
 
 
+class TorchAllocator:
+    """Device memory for a handle from torch's caching allocator (the
+    library's dev_alloc / dev_free callbacks): blocks are taken on the
+    handle's stream and returned to torch's cache when the handle frees them.
+    Counts calls and failures (``fail_after``: the allocation with this
+    0-based number and every later one fail, for tests of the library's
+    out-of-memory path)."""
+
+    def __init__(self, device=None, fail_after=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self.fail_after = fail_after
+        self.allocs = 0
+        self.frees = 0
+        self.failed = 0
+        self.live = {}
+        self._alloc = ALLOC_FN(self._alloc_cb)
+        self._free = FREE_FN(self._free_cb)
+
+    def _alloc_cb(self, ctx, nbytes, stream):
+        import torch
+        if self.fail_after is not None and self.allocs >= self.fail_after:
+            self.failed += 1
+            return None
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=int(stream or 0))
+        except Exception:
+            self.failed += 1
+            return None
+        self.allocs += 1
+        self.live[p] = int(nbytes)
+        return p
+
+    def _free_cb(self, ctx, ptr, stream):
+        import torch
+        self.frees += 1
+        self.live.pop(ptr, None)
+        torch.cuda.caching_allocator_delete(ptr)
+
+
 def _ptr(x):
     if _is_device(x):
         return ctypes.c_void_p(x.data_ptr())
@@ -131,7 +198,12 @@ class Stdecomp:
     """One SGD_Tucker model on the GPU (a libstdecomp handle)."""
 
     def __init__(self, dims, ranks, idx, vals, batch=256, lr_factor=0.01, lr_core=0.01, lam_factor=0.01,
-                 lam_core=0.01, seed_sample=0, seed_init=0, init="scaled", dtype="f32", chunk=0, stream=None):
+                 lam_core=0.01, seed_sample=0, seed_init=0, init="scaled", dtype="f32", chunk=0, stream=None,
+                 allocator=None, train_rmse=False, r_core=0):
+        """allocator: None (the library calls hipMalloc) or a TorchAllocator
+        (every device buffer of the handle from torch's caching allocator);
+        train_rmse: epoch() also reports the RMSE over the training set;
+        r_core: 0 for a dense core, R > 0 for the Kruskal core of rank R."""
         L = load()
         self.N = len(dims)
         self.dims = tuple(int(d) for d in dims)
@@ -159,6 +231,13 @@ class Stdecomp:
         opt.inputs_on_device = 1 if on_dev else 0
         opt.chain_chunk = chunk
         opt.stream = ctypes.c_void_p(stream) if stream else None
+        opt.report_train_rmse = 1 if train_rmse else 0
+        opt.r_core = int(r_core)
+        self.r_core = int(r_core)
+        self.allocator = allocator  # kept alive as long as the handle: the library calls it
+        if allocator is not None:
+            opt.dev_alloc = allocator._alloc
+            opt.dev_free = allocator._free
         h = ctypes.c_void_p()
         rc = L.stdecomp_init(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h))
         if rc != STD_OK:
@@ -166,6 +245,7 @@ class Stdecomp:
         self._h = h
         self.nnz = nnz
         self.batch = batch
+        _live.add(self)
 
     def _check(self, rc, what):
         if rc != STD_OK:
@@ -175,6 +255,7 @@ class Stdecomp:
         if getattr(self, "_h", None):
             load().stdecomp_free(self._h)
             self._h = None
+            _live.discard(self)
 
     def __del__(self):
         try:
@@ -242,6 +323,19 @@ class Stdecomp:
         ptrs = (ctypes.c_void_p * self.N)(*[a.ctypes.data for a in A])
         self._check(load().stdecomp_set_params(self._h, ptrs, _ptr(G)), "stdecomp_set_params")
 
+    def get_kruskal(self):
+        """The Kruskal factors B(n) (J_n x R each) of a handle with r_core > 0."""
+        B = [np.empty((J, self.r_core), np.float32) for J in self.ranks]
+        ptrs = (ctypes.c_void_p * self.N)(*[b.ctypes.data for b in B])
+        self._check(load().stdecomp_get_kruskal(self._h, ptrs), "stdecomp_get_kruskal")
+        return B
+
+    def set_kruskal(self, B):
+        """Set the Kruskal factors (and the core to their product)."""
+        B = [np.ascontiguousarray(b, np.float32) for b in B]
+        ptrs = (ctypes.c_void_p * self.N)(*[b.ctypes.data for b in B])
+        self._check(load().stdecomp_set_kruskal(self._h, ptrs), "stdecomp_set_kruskal")
+
     def set_epoch(self, e):
         self._check(load().stdecomp_set_epoch(self._h, e), "stdecomp_set_epoch")
 
@@ -284,10 +378,20 @@ def epoch_batched(handles, n_epochs=1):
     return [{f: getattr(s, f) for f, _ in EpochStats._fields_} for s in st]
 
 
-def sample_order(T, seed, epoch):
-    """The GPU sampler: pi_e(q) for q in [0, T)."""
-    out = np.empty(T, np.int64)
-    rc = load().stdecomp_sample_order(T, seed, epoch, out.ctypes.data_as(_i64p))
+def sample_order(T, seed, epoch, device=False, stream=None):
+    """The GPU sampler: pi_e(q) for q in [0, T), as a numpy array, or with
+    ``device`` a torch int64 tensor written in place on the device (on
+    ``stream``, a hipStream_t value, or the null stream)."""
+    if device:
+        import torch
+        out = torch.empty(T, dtype=torch.int64, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        rc = load().stdecomp_sample_order(T, seed, epoch, ctypes.c_void_p(out.data_ptr()), 1,
+                                          ctypes.c_void_p(stream) if stream else None)
+    else:
+        out = np.empty(T, np.int64)
+        rc = load().stdecomp_sample_order(T, seed, epoch, ctypes.c_void_p(out.ctypes.data), 0,
+                                          ctypes.c_void_p(stream) if stream else None)
     if rc != STD_OK:
         raise StdecompError(rc, "stdecomp_sample_order")
     return out

@@ -106,6 +106,13 @@ __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed
   return *flag_lds != 0;
 }
 
+// Record a non-finite parameter write (integer atomic; the plain load skips
+// the atomic once an earlier location is known, so a diverged chain does not
+// pay one atomic per write).
+__device__ __forceinline__ void report_nonfinite(const ChainArgs& a, unsigned long long key) {
+  if (key < *reinterpret_cast<volatile unsigned long long*>(a.nf)) atomicMin(a.nf, key);
+}
+
 // ---------------------------------------------------------------------------
 // The record a lane handles in one phase: minibatch order for the core
 // sub-step, (row, position) order of mode ph-1 for the factor sub-steps.
@@ -287,7 +294,7 @@ __device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int 
 // writes the rows (master, and BF16 copy in BF16 mode).
 template <int JR, bool EXACT, bool BF, bool GROUPED>
 __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
-                                  const float* cbuf, float* split, int sstride, bool store) {
+                                  const float* cbuf, float* split, int sstride, bool store, int64_t kb) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = EXACT ? JR : a.s.J[pm];
   const int NS = 2 * a.W;
@@ -436,6 +443,7 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
       const float v = split[en * sstride + 4 + j];
       a.A[pm][(int64_t)row * a.s.Jp[pm] + j] = v;
       if (BF) a.Ab[pm][(int64_t)row * a.Jb[pm] + j] = bf16_bits(v);
+      if (!__builtin_isfinite(v)) report_nonfinite(a, nf_key(kb, pm + 1, row));
     }
   }
 }
@@ -1158,6 +1166,192 @@ __device__ __forceinline__ void copy_carry(const ChainArgs& a, int par, float* c
 }
 
 // ---------------------------------------------------------------------------
+// Kruskal core sub-step (Section "Optimization Process for the Core Tensor",
+// Eqs. CP-Decomposition, eventual0, Q_r, eventual_approximated,
+// Gradient_core_tensor; Algorithm 1, core loop).  The core is the Kruskal
+// product G = sum_r b(1)_r o ... o b(N)_r of B(n) in R^{J_n x R}; for each
+// mode n in turn, every column b_c of B(n) in turn takes the averaged SGD
+// step on (1/2m) ||x - sum_r W_r b_r||^2 + (lambda/2) ||b_c||^2 with
+//   W_r[p, a] = a(n)_p[a] prod_{k != n} (a(k)_p . b(k)_r)
+// (the rows of H_Psi O_r, which depend on the other modes' B only), i.e.
+//   b_c <- b_c - gG ( V_c / m + lG b_c ),  V_c = -W_c^T x + sum_r W_c^T W_r b_r.
+// Each workgroup forms the Gram matrix of [W_0 .. W_{R-1} | x] over its
+// chunk's samples (packed upper triangle), the workgroups' matrices are
+// summed in a fixed order (each reduces a slice, one grid barrier, then all
+// read the sum), and every workgroup takes the R column steps identically on
+// the summed matrix.  Two grid barriers per mode; then G is formed from B.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tri_index(int e1, int e2, int ke) { return e1 * ke - ((e1 * (e1 - 1)) >> 1) + (e2 - e1); }
+
+template <int JR, bool BF, bool EXACT>
+__device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, int cnt, const float* rowbuf, float x,
+                                  unsigned& passed, int* flag_lds) {
+  extern __shared__ float lds[];
+  const ChainLayout& L = a.lay;
+  const Shape& s = a.s;
+  const int N = s.N, R = a.R, tid = threadIdx.x, BT = blockDim.x, chp = L.chp;
+  float* Bs = lds + L.kb;
+  float* wt = lds + L.kwt;
+  float* g = lds + L.kg;  // full symmetric matrix, ke x ke (row stride ke)
+  const int klgp = pad4(L.klg);
+  const float inv_m = 1.0f / (float)m;
+  for (int n = 0; n < N; ++n) {
+    const int Jn = EXACT ? JR : s.J[n];
+    const int E = R * Jn;
+    const int ke = E + 1;
+    const int lg = (ke * (ke + 1)) >> 1;
+    const int nb4 = (ke + 3) >> 2;
+    const int kpar = n & 1;  // partial buffers alternate between modes
+    // 1. rows of [W_0 .. W_{R-1} | x] for the chunk's samples (zero beyond the count)
+    if (tid < chp) {
+      float* wrow = wt + tid * L.kws;
+      if (tid < cnt) {
+        float an[JR];
+        read_row<JR, BF, EXACT>(rowbuf, L.coff[n], chp, tid, Jn, an);
+        for (int c = 0; c < R; ++c) {
+          float q = 1.f;
+          for (int k = 0; k < N; ++k) {
+            if (k == n) continue;
+            const int Jk = EXACT ? JR : s.J[k];
+            const float* bk = Bs + L.kboff[k] + c;
+            float d = 0.f;
+            for (int j = 0; j < Jk; ++j) d = fmaf(row_at<BF>(rowbuf, L.coff[k], chp, tid, j), bk[j * R], d);
+            q *= d;
+          }
+#pragma unroll
+          for (int aa = 0; aa < JR; ++aa)
+            if (EXACT || aa < Jn) wrow[c * Jn + aa] = an[aa] * q;
+        }
+        wrow[E] = x;
+      } else {
+        for (int e = 0; e < ke; ++e) wrow[e] = 0.f;
+      }
+      for (int e = ke; e < 4 * nb4; ++e) wrow[e] = 0.f;
+    }
+    __syncthreads();
+    // 2. this chunk's Gram matrix, packed upper triangle, in 4 x 4 blocks
+    float* part = a.partial + ((size_t)kpar * a.W + w) * klgp;
+    const int npairs = (nb4 * (nb4 + 1)) >> 1;
+    for (int pi = tid; pi < npairs; pi += BT) {
+      int bi = 0, rem = pi;
+      while (rem >= nb4 - bi) {
+        rem -= nb4 - bi;
+        ++bi;
+      }
+      const int bj = bi + rem;
+      f32x4 acc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int p = 0; p < chp; ++p) {
+        const f32x4 u = *reinterpret_cast<const f32x4*>(wt + p * L.kws + 4 * bi);
+        const f32x4 v = *reinterpret_cast<const f32x4*>(wt + p * L.kws + 4 * bj);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += u[i] * v;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int e1 = 4 * bi + i, e2 = 4 * bj + jj;
+          if (e1 <= e2 && e2 < ke) part[tri_index(e1, e2, ke)] = acc[i][jj];
+        }
+    }
+    passed += 1;
+    barrier_arrive(a, w, passed);
+    if (!barrier_wait(a, passed, flag_lds)) return false;
+    // 3. this workgroup's slice of the sum over workgroups (groups of threads
+    //    add runs of workgroups in order, then the groups are added in order)
+    {
+      const float* pb = a.partial + (size_t)kpar * a.W * klgp;
+      float* gs = a.partial + (size_t)2 * a.W * klgp + (size_t)kpar * klgp;
+      const int per = (lg + a.W - 1) / a.W;
+      const int e0 = w * per, e1 = min(lg, e0 + per);
+      if (per <= BT) {
+        const int ng = min(BT / per, a.W), vg = (a.W + ng - 1) / ng;
+        const int i = tid % per, grp = tid / per;
+        if (grp < ng) {
+          float sum = 0.f;
+          if (e0 + i < e1)
+            for (int v = grp * vg; v < min(a.W, (grp + 1) * vg); ++v) sum += pb[(size_t)v * klgp + e0 + i];
+          g[grp * per + i] = sum;
+        }
+        __syncthreads();
+        if (tid < per && e0 + tid < e1) {
+          float sum = 0.f;
+          for (int g2 = 0; g2 < ng; ++g2) sum += g[g2 * per + tid];
+          gs[e0 + tid] = sum;
+        }
+      } else {
+        for (int e = e0 + tid; e < e1; e += BT) {
+          float sum = 0.f;
+          for (int v = 0; v < a.W; ++v) sum += pb[(size_t)v * klgp + e];
+          gs[e] = sum;
+        }
+      }
+    }
+    passed += 1;
+    barrier_arrive(a, w, passed);
+    if (!barrier_wait(a, passed, flag_lds)) return false;
+    // 4. the summed matrix, unpacked (every workgroup)
+    {
+      const float* gs = a.partial + (size_t)2 * a.W * klgp + (size_t)kpar * klgp;
+      for (int e = tid; e < ke * ke; e += BT) {
+        const int r1 = e / ke, c1 = e - r1 * ke;
+        g[e] = gs[r1 <= c1 ? tri_index(r1, c1, ke) : tri_index(c1, r1, ke)];
+      }
+    }
+    __syncthreads();
+    // 5. the column steps, c = 0 .. R-1 in order: row a of V_c by a group of
+    //    TPR lanes (a power of two within one wave), summed by xor shuffles
+    {
+      float* Bn = Bs + L.kboff[n];
+      int tpr = 64;
+      while (tpr > 1 && tpr * Jn > BT) tpr >>= 1;
+      const int ra = tid / tpr, l = tid % tpr;
+      for (int c = 0; c < R; ++c) {
+        float V = 0.f;
+        if (ra < Jn) {
+          const float* grow = g + (c * Jn + ra) * ke;
+          for (int e2 = l; e2 < E; e2 += tpr) {
+            const int r = e2 / Jn, bb = e2 - r * Jn;
+            V = fmaf(grow[e2], Bn[bb * R + r], V);
+          }
+        }
+        for (int off = 1; off < tpr; off <<= 1) V += __shfl_xor(V, off, 64);
+        float old = 0.f;
+        if (ra < Jn) {
+          V -= g[(c * Jn + ra) * ke + E];  // - (W_c^T x)[a]
+          old = Bn[ra * R + c];
+        }
+        __syncthreads();  // every group has read b_c
+        if (ra < Jn && l == 0) {
+          const float nb = old - a.gG * (V * inv_m + a.lG * old);
+          Bn[ra * R + c] = nb;
+          if (!__builtin_isfinite(nb)) report_nonfinite(a, nf_key(b, 0, L.kboff[n] + ra * R + c));
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // 6. the core of the updated B: G[lin] = sum_r prod_k B(k)[j_k, r]
+  float* Gs = lds + L.gs;
+  for (int lin = tid; lin < s.P; lin += BT) {
+    float acc = 0.f;
+    for (int r = 0; r < R; ++r) {
+      float t = 1.f;
+      for (int k = 0; k < N; ++k) {
+        const int jk = (lin / s.lstride[k]) % s.J[k];
+        t *= Bs[L.kboff[k] + jk * R + r];
+      }
+      acc += t;
+    }
+    Gs[lin] = acc;
+  }
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // The chain kernel.  Workgroup w owns positions [w*chunk, (w+1)*chunk) of
 // every minibatch: in minibatch order for the core sub-step, in (row,
 // position) order for the factor sub-steps.
@@ -1184,7 +1378,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
   constexpr int JR = JU ? JU : kMaxRank;
   constexpr int NM = NU ? NU : kMaxOrder;  // modes the per-mode loops cover
   constexpr bool EXACT = JU != 0;
-  constexpr bool BF = BFI != 0;
+  constexpr bool BF = (BFI & 1) != 0;
+  constexpr bool KR = (BFI & 2) != 0;  // Kruskal core (a.R > 0)
   constexpr bool TS = NU != 3;  // two-stage contraction (layout of the tables)
   extern __shared__ float lds[];
   const Shape& s = a.s;
@@ -1196,7 +1391,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const ChainLayout& L = a.lay;
-  const bool CORE2 = NU != 3 && L.core2;  // two-level core update (never planned for three modes)
+  const bool CORE2 = !KR && NU != 3 && L.core2;  // two-level core update (never planned for three modes)
 
   float* Gs = lds + L.gs;
   float* TB = lds + L.tb;
@@ -1222,6 +1417,10 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
 
   // ---- set-up: core, index maps, resident tables
   for (int lin = tid; lin < P; lin += BT) Gs[lin] = a.G[lin];
+  if constexpr (KR) {
+    const int nb = L.kboff[N - 1] + s.J[N - 1] * a.R;
+    for (int i = tid; i < nb; i += BT) lds[L.kb + i] = a.B[i];
+  }
   // (both row buffers and a zero tail: the MFMA K steps read up to 31 words past a row)
   for (int i = tid; i < 2 * L.rowsz + kRowTail; i += BT) rows0[i] = 0.f;
   for (int i = tid; i < L.aux_len; i += BT) {
@@ -1300,7 +1499,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
           }
           if (tid == 0) xc = xsrc[2 * a.W];
         }
-        if (ph == 1 && !CORE2 && tid < P4) {
+        if (!KR && ph == 1 && !CORE2 && tid < P4) {
 #pragma unroll
           for (int v = 0; v < 8; ++v)
             if (v < a.W) pp[v] = psrc[(size_t)v * P4 + tid];
@@ -1340,7 +1539,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       const bool has_next = nbb < a.b_end;
 
       // ---- 2. core: finish the core step of this minibatch
-      if (ph == 1 && CORE2) {
+      if (KR && ph == 1) {
+        // (the Kruskal core sub-step formed G in phase 0)
+        if (L.tb_all)
+          build_table_map<BF>(Gs, tmap + pt.tb_off, pt.tb_len, BF ? TB + (pt.tb_off >> 1) : TB + pt.tb_off);
+      } else if (ph == 1 && CORE2) {
         // two levels: this workgroup's slice of G, one grid barrier, then all of G
         f32x4* red = reinterpret_cast<f32x4*>(lds + L.red);
         const int i = tid % L.cper, grp = tid / L.cper;
@@ -1360,7 +1563,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int lin = 4 * l4 + e;
-            if (lin < P) a.G[lin] = Gs[lin] - a.gG * (-sum[e] * inv_m + a.lG * Gs[lin]);
+            if (lin < P) {
+              const float g = Gs[lin] - a.gG * (-sum[e] * inv_m + a.lG * Gs[lin]);
+              a.G[lin] = g;
+              if (!__builtin_isfinite(g)) report_nonfinite(a, nf_key(b, 0, lin));
+            }
           }
         }
         passed += 1;
@@ -1400,8 +1607,14 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) gv[i] = Gs[min(4 * l4 + i, P - 1)];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (4 * l4 + i < P) Gs[4 * l4 + i] = gv[i] - a.gG * (-sum[i] * inv_m + a.lG * gv[i]);
+          for (int i = 0; i < 4; ++i) {
+            if (4 * l4 + i < P) {
+              const float g = gv[i] - a.gG * (-sum[i] * inv_m + a.lG * gv[i]);
+              Gs[4 * l4 + i] = g;
+              // (every workgroup checks its own copy before it writes any row of this phase)
+              if (!__builtin_isfinite(g)) report_nonfinite(a, nf_key(b, 0, 4 * l4 + i));
+            }
+          }
         }
         __syncthreads();
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival
@@ -1412,7 +1625,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
         const int nsplit = misc[0];
-        finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0);
+        finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0,
+                                                  ph == 0 ? b - 1 : b);
         // the schedule says which entry (if any) holds this sample's mode-pm row
         const int pe = (cur.meta >> kMetaPatchShift) & 0xFF;
         if (active && pe > 0) {
@@ -1442,6 +1656,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       // ---- 5. E_p for every sample of the chunk
       constexpr bool HPV = NU == 3;  // one remaining mode: hp is a view of its rows
       HpRef<HPV, BF> hpr;
+      if (KR && ph == 0) {
+        // ================= Kruskal core sub-step =================
+        __syncthreads();  // (rows patched by other threads above)
+        if (!kruskal_core_step<JR, BF, EXACT>(a, w, b, m, cnt, rowbuf, cur.x, passed, misc + 7)) return;
+      } else {
       if constexpr (HPV) {
         hpr = HpRef<HPV, BF>{rowbuf, chp, pt.c_hi};
       } else {
@@ -1538,14 +1757,17 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
             float* arow = a.A[n] + (int64_t)row * s.Jp[n];
             unsigned short* brow = BF ? a.Ab[n] + (int64_t)row * a.Jb[n] : nullptr;
             const float inv_c = 1.0f / (float)c;
+            bool fin = true;
 #pragma unroll
             for (int j = 0; j < JR; ++j) {
               if (EXACT || j < Jn) {
                 const float v = an[j] - a.gA * (u[j] * inv_c + a.lA * an[j]);
                 arow[j] = v;
                 if (BF) brow[j] = bf16_bits(v);
+                fin = fin && __builtin_isfinite(v);
               }
             }
+            if (!fin) report_nonfinite(a, nf_key(b, ph, row));
           } else {
             // element-major carry slots (element e of slot sl at e * 2W + sl)
             const int NS = 2 * a.W;
@@ -1562,6 +1784,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
           }
         }
       }
+      }  // (Kruskal core sub-step, or the contraction and the sub-step)
       // ---- 6. barrier: the next sub-step needs this one's result.  Between
       //      arrival and wait (no reads of what other workgroups write): build
       //      the resident tables the core update changed, or, with one table
@@ -1610,10 +1833,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
     if (tid == 0) misc[0] = xsrc[2 * a.W];
     copy_carry(a, ppar, cbuf);
     __syncthreads();
-    finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true);
+    finish_split_rows<JR, EXACT, BF, NU != 3>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true, a.b_end - 1);
   }
-  if (w == 0)
+  if (w == 0) {
     for (int lin = tid; lin < P; lin += BT) a.G[lin] = Gs[lin];
+    if constexpr (KR) {
+      const int nb = L.kboff[N - 1] + s.J[N - 1] * a.R;
+      for (int i = tid; i < nb; i += BT) a.B[i] = lds[L.kb + i];
+    }
+  }
 }
 
 template <int JU, int NU, int BFI>
@@ -1736,8 +1964,29 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     L.cgrp = grp;
     L.cvg = vg;
   }
+  if (a.R > 0) L.core2 = 0;  // the Kruskal core has its own reduction
+  // Kruskal core: B resident, and the [W | x] rows and their Gram matrix in
+  // the space of the hp / E / r a(0) regions (grown if they are smaller)
+  size_t kr_extra = 0;
+  L.kb = L.kwt = L.kg = L.kws = L.ke = L.klg = 0;
+  for (int k = 0; k < kMaxOrder; ++k) L.kboff[k] = 0;
+  if (a.R > 0) {
+    int o = 0;
+    for (int k = 0; k < N; ++k) {
+      L.kboff[k] = o;
+      o += s.J[k] * a.R;
+    }
+    L.ke = a.R * jmax + 1;
+    L.kws = pad4(L.ke);
+    L.klg = (L.ke * (L.ke + 1)) / 2;
+    const size_t need = al((size_t)L.chp * L.kws) + al(std::max((size_t)L.ke * L.ke, (size_t)threads));
+    const size_t have = al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) + al((size_t)L.chp * L.ras);
+    kr_extra = need > have ? need - have : 0;
+  }
+  const size_t kb_len = a.R > 0 ? al((size_t)(L.kboff[N - 1] + s.J[N - 1] * a.R)) : 0;
   const size_t red_len = L.core2 ? (size_t)L.cgrp * L.cper * 4 : 0;
-  size_t common = al(red_len) + al(s.P) + al(2 * (size_t)L.rowsz + kRowTail) + al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) +
+  size_t common = al(red_len) + kb_len + kr_extra + al(s.P) + al(2 * (size_t)L.rowsz + kRowTail) +
+                  al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) +
                   al((size_t)L.chp * L.ras) + al((size_t)a.split_cap * L.sstride) +
                   al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0) + al((size_t)hm_len) +
                   al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
@@ -1751,7 +2000,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   off += al(2 * (size_t)L.rowsz + kRowTail);
   L.hp = (int)off;    off += al((size_t)khimax * L.hs);
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
-  L.ra = (int)off;    off += al((size_t)L.chp * L.ras);
+  L.ra = (int)off;    off += al((size_t)L.chp * L.ras) + kr_extra;
+  L.kwt = L.hp;
+  L.kg = L.hp + (int)al((size_t)L.chp * L.kws);
+  L.kb = (int)off;    off += kb_len;
   L.split = (int)off; off += al((size_t)a.split_cap * L.sstride);
   L.cbuf = (int)off;  off += al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0);
   L.hmap = (int)off;  off += al((size_t)hm_len);
@@ -1923,6 +2175,11 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
         chk.lay.ints != a.lay.ints || chk.lay.tmap != a.lay.tmap || chk.lay.aux_len != a.lay.aux_len ||
         chk.lay.hm_len != a.lay.hm_len || !a.aux)
       return hipErrorInvalidValue;
+  }
+  if (a.R > 0) {  // Kruskal core: the generic-rank kernels
+    const bool n3 = a.s.N == 3;
+    if (a.bf16) return n3 ? launch_chain_t<0, 3, 3>(a, threads, bytes, st) : launch_chain_t<0, 0, 3>(a, threads, bytes, st);
+    return n3 ? launch_chain_t<0, 3, 2>(a, threads, bytes, st) : launch_chain_t<0, 0, 2>(a, threads, bytes, st);
   }
   hipError_t e = hipSuccess;
   if (a.bf16) {

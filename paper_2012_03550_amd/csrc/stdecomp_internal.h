@@ -53,6 +53,15 @@ struct ChainLayout {
   int coff[kMaxOrder];
   int ctot;     // chunks per sample over all modes
   int rowsz;    // floats of one row buffer
+  // Kruskal core (R > 0): kb = the matrices B(k) (J_k x R row-major, B(k) at
+  // kb + kboff[k]); kwt = the chunk's rows of [W_0 .. W_{R-1} | x] for the
+  // current mode (chp rows of stride kws: entry c J_n + a, then x at R J_n);
+  // kg = the packed upper triangle of their Gram matrix (ke = R Jmax + 1
+  // columns at most).  kwt and kg overlay the hp / E / r a(0) regions, which
+  // the Kruskal core sub-step does not use.
+  int kb, kwt, kg, kws, ke;
+  int kboff[kMaxOrder];
+  int klg;      // floats of the packed triangle for ke columns: ke (ke + 1) / 2
 };
 
 // Per-phase constants of the chain, built on the host.  Phase 0 is the core
@@ -93,6 +102,15 @@ __host__ __device__ inline int xrow_stride(int W) { return 2 * W + 4; }
 constexpr int kMetaTail = 1 << 9, kMetaBefore = 1 << 10, kMetaAfter = 1 << 11;
 constexpr int kMetaPatchShift = 16;
 
+// Location of a non-finite parameter written by the chain, ordered as the
+// chain writes them: minibatch b (saturated at 2^29 - 1), phase ph (0: the
+// core, whose "row" is the flat core index; ph >= 1: a row of mode ph - 1),
+// row.  The smallest key over a run is the first non-finite value.
+__host__ __device__ inline unsigned long long nf_key(int64_t b, int ph, int64_t row) {
+  const unsigned long long bb = b < ((1ll << 29) - 1) ? (unsigned long long)b : ((1ull << 29) - 1);
+  return ((bb * 16ull + (unsigned long long)ph) << 31) | (unsigned long long)(row & 0x7FFFFFFF);
+}
+
 // Arguments of the persistent minibatch chain kernel.
 struct ChainArgs {
   Shape s;
@@ -107,10 +125,14 @@ struct ChainArgs {
   int Jb[kMaxOrder];        // row stride of the BF16 copies (J_n rounded up to 8)
   int bf16;                 // 1: BF16 operands, FP32 masters and accumulation
   float* G;                 // FP32 master core (P)
-  float* partial;           // [W][pad4(P)] per-workgroup core-gradient partials
+  int R;                    // Kruskal rank of the core (0: dense core)
+  float* B;                 // Kruskal core: FP32 masters of B(k), J_k x R each, back to back (R > 0)
+  float* partial;           // [W][pad4(P)] per-workgroup core-gradient partials; Kruskal core:
+                            // [2][W][pad4(klg)] Gram partials then [2][pad4(klg)] their sums
   float* carry;             // [2][W][2][carry_stride] per-chunk run partials and old rows
   unsigned* bar;            // grid-barrier arrival flags, one per workgroup, kFlagStride apart (zero at launch)
   int* err;                 // set to nonzero by a workgroup that gives up
+  unsigned long long* nf;   // earliest non-finite write: nf_key(b, phase, row), all ones if none
   int64_t T, M;
   int64_t b_begin, b_end;   // minibatches [b_begin, b_end) of the epoch
   float gA, lA, gG, lG;     // learning steps and L2 weights

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -46,10 +47,14 @@ struct stdecomp_handle {
   uint16_t* Ab[kMaxOrder] = {};  // BF16 read copies (BF16 mode)
   int Jb[kMaxOrder] = {};
   float* G = nullptr;
+  int R = 0;             // Kruskal rank of the core (0: dense core)
+  float* B = nullptr;    // Kruskal core: B(n), J_n x R each, back to back
+  int64_t nB = 0;        // floats of B
   float* partial = nullptr;
   float* carry = nullptr;
   unsigned* bar = nullptr;
   int* err = nullptr;
+  unsigned long long* nf = nullptr;  // first non-finite write of the chain (stdk::nf_key), all ones if none
   double* dscratch = nullptr;  // loss/sum-of-squares block partials
   int dscratch_blocks = 0;
   int* flag = nullptr;
@@ -57,12 +62,13 @@ struct stdecomp_handle {
   int64_t sched_epoch = -1;  // epoch whose schedule coo_perm/sigma hold
   std::string last_error;
   hipEvent_t ev[4] = {};
+  stdecomp_alloc_fn dev_alloc = nullptr;  // caller's device allocator (NULL: hipMalloc)
+  stdecomp_free_fn dev_free = nullptr;
+  void* alloc_ctx = nullptr;
+  bool train_rmse = false;  // epoch stats carry the training RMSE
 };
 
 namespace {
-
-constexpr int kBatchesPerLaunch = 2048;  // bounds the duration of one chain launch
-constexpr long long kSpinLimit = 1ll << 24;
 
 int fail(stdecomp_handle* h, int code, const std::string& msg) {
   if (h) h->last_error = msg;
@@ -80,23 +86,51 @@ int hip_fail(stdecomp_handle* h, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
   } while (0)
 
+// Device workspace of stdecomp_epoch_batched (argument table and workgroup
+// map), one per device, kept for the life of the process.
+struct BatchWorkspace {
+  struct Dev {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::mutex mu;
+  Dev dev[64];
+};
+BatchWorkspace g_batch_ws;
+
+constexpr int kBatchesPerLaunch = 2048;  // bounds the duration of one chain launch
+constexpr long long kSpinLimit = 1ll << 24;
+
+
+// Device memory of a handle: from the caller's allocator when the options
+// give one (stdecomp_options.dev_alloc / dev_free), else hipMalloc / hipFree.
 template <typename T>
 int dalloc(stdecomp_handle* h, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(h, STD_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  const size_t bytes = count * sizeof(T);
+  if (h->dev_alloc) {
+    void* q = h->dev_alloc(h->alloc_ctx, bytes, (void*)h->stream);
+    if (!q) return fail(h, STD_E_NOMEM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    *p = static_cast<T*>(q);
+  } else {
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return fail(h, STD_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
   }
-  h->device_bytes += count * sizeof(T);
+  h->device_bytes += bytes;
   return STD_OK;
 }
 
 template <typename T>
-void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+void dfree(stdecomp_handle* h, T*& p) {
+  if (p) {
+    if (h->dev_free) h->dev_free(h->alloc_ctx, (void*)p, (void*)h->stream);
+    else (void)hipFree((void*)p);
+  }
   p = nullptr;
 }
 
@@ -160,6 +194,7 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
     h->carry_stride = stdk::pad4(2 + 2 * jmax);
     stdk::ChainArgs a{};
     a.s = s;
+    a.R = h->R;
     a.W = W;
     a.chunk = chunk;
     a.split_cap = h->split_cap;
@@ -204,10 +239,13 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.lay = h->lay;
   for (int i = 0; i <= kMaxOrder; ++i) a.pt[i] = h->pt[i];
   a.G = h->G;
+  a.R = h->R;
+  a.B = h->B;
   a.partial = h->partial;
   a.carry = h->carry;
   a.bar = h->bar;
   a.err = h->err;
+  a.nf = h->nf;
   a.T = h->T;
   a.M = h->M;
   a.gA = h->gA;
@@ -253,7 +291,7 @@ int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const
     if (vals) {
       rc = dalloc(h, &tvals, (size_t)n);
       if (rc) {
-        dfree(tidx);
+        dfree(h, tidx);
         return rc;
       }
       h->device_bytes -= (size_t)n * 4;
@@ -265,8 +303,8 @@ int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const
   uint32_t* rec = nullptr;
   int rc = dalloc(h, &rec, (size_t)n * h->s.R);
   if (rc) {
-    dfree(tidx);
-    dfree(tvals);
+    dfree(h, tidx);
+    dfree(h, tvals);
     return rc;
   }
   h->device_bytes -= (size_t)n * h->s.R * 4;
@@ -275,14 +313,14 @@ int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const
   int bad = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(tidx);
-  dfree(tvals);
+  dfree(h, tidx);
+  dfree(h, tvals);
   if (e != hipSuccess) {
-    dfree(rec);
+    dfree(h, rec);
     return hip_fail(h, e, "packing entries");
   }
   if (bad) {
-    dfree(rec);
+    dfree(h, rec);
     return fail(h, STD_E_INVAL, "index out of range");
   }
   *rec_out = rec;
@@ -324,27 +362,59 @@ int refresh_bf16(stdecomp_handle* h) {
   return STD_OK;
 }
 
+// Floats of the chain's partial buffer: per-workgroup core-gradient partials
+// (dense core) or, for the Kruskal core, two sets of per-workgroup Gram
+// partials and two summed Gram matrices (packed triangles).
+size_t partial_floats(const stdecomp_handle* h) {
+  size_t n = (size_t)h->W * stdk::pad4(h->s.P);
+  if (h->R > 0) {
+    const size_t klgp = (size_t)stdk::pad4(h->lay.klg);
+    const size_t k = 2 * (size_t)h->W * klgp + 2 * klgp;
+    n = k > n ? k : n;
+  }
+  return n;
+}
+
+// G = sum_r prod_k B(k)[j_k, r] on the host (Eq. CP-Decomposition; G flat with
+// j_1 fastest, B(k) J_k x R row-major, back to back).
+void kruskal_product_host(const stdk::Shape& s, int R, const float* B, std::vector<float>& G) {
+  G.assign((size_t)s.P, 0.f);
+  std::vector<int64_t> off(s.N, 0);
+  for (int k = 1; k < s.N; ++k) off[k] = off[k - 1] + (int64_t)s.J[k - 1] * R;
+  for (int lin = 0; lin < s.P; ++lin) {
+    double acc = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double t = 1.0;
+      for (int k = 0; k < s.N; ++k) t *= B[off[k] + (int64_t)((lin / s.lstride[k]) % s.J[k]) * R + r];
+      acc += t;
+    }
+    G[lin] = (float)acc;
+  }
+}
+
 void release(stdecomp_handle* h) {
   if (!h) return;
-  dfree(h->coo);
-  dfree(h->coo_perm);
-  dfree(h->sigma);
-  dfree(h->rec_sorted);
-  dfree(h->xrow);
-  dfree(h->nseg);
-  dfree(h->meta);
-  dfree(h->aux);
+  dfree(h, h->coo);
+  dfree(h, h->coo_perm);
+  dfree(h, h->sigma);
+  dfree(h, h->rec_sorted);
+  dfree(h, h->xrow);
+  dfree(h, h->nseg);
+  dfree(h, h->meta);
+  dfree(h, h->aux);
   for (int n = 0; n < kMaxOrder; ++n) {
-    dfree(h->A[n]);
-    dfree(h->Ab[n]);
+    dfree(h, h->A[n]);
+    dfree(h, h->Ab[n]);
   }
-  dfree(h->G);
-  dfree(h->partial);
-  dfree(h->carry);
-  dfree(h->bar);
-  dfree(h->err);
-  dfree(h->dscratch);
-  dfree(h->flag);
+  dfree(h, h->G);
+  dfree(h, h->B);
+  dfree(h, h->partial);
+  dfree(h, h->carry);
+  dfree(h, h->bar);
+  dfree(h, h->err);
+  dfree(h, h->nf);
+  dfree(h, h->dscratch);
+  dfree(h, h->flag);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -393,9 +463,11 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     return STD_E_INVAL;
   if (o->init_kind < STD_INIT_SCALED || o->init_kind > STD_INIT_CALLER) return STD_E_INVAL;
   if (o->dtype != STD_DTYPE_F32 && o->dtype != STD_DTYPE_BF16) return STD_E_INVAL;
-  if (o->r_core != 0) return STD_E_INVAL;
-  for (int i = 0; i < 15; ++i)
+  if (o->r_core < 0 || o->r_core > 64) return STD_E_INVAL;
+  for (int i = 0; i < 11; ++i)
     if (o->reserved[i] != 0) return STD_E_INVAL;
+  if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr)) return STD_E_INVAL;
+  if (o->report_train_rmse != 0 && o->report_train_rmse != 1) return STD_E_INVAL;
   int64_t P = 1;
   for (int n = 0; n < N; ++n) {
     if (p->dims[n] < 1 || p->dims[n] >= (1ll << 31) || p->ranks[n] < 1 || p->ranks[n] > kMaxRank)
@@ -407,6 +479,10 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
 
   stdecomp_handle* h = new (std::nothrow) stdecomp_handle();
   if (!h) return STD_E_NOMEM;
+  h->dev_alloc = o->dev_alloc;
+  h->dev_free = o->dev_free;
+  h->alloc_ctx = o->alloc_ctx;
+  h->train_rmse = o->report_train_rmse != 0;
   auto bail = [&](int rc) {
     std::fprintf(stderr, "stdecomp_init: %s\n", h->last_error.c_str());
     release(h);
@@ -454,6 +530,9 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   h->lG = o->lambda_core;
   h->seed_sample = o->seed_sample;
   h->dtype = o->dtype;
+  h->R = o->r_core;
+  h->nB = 0;
+  for (int n = 0; n < N; ++n) h->nB += (int64_t)s.J[n] * h->R;
   if (o->stream) {
     h->stream = (hipStream_t)o->stream;
   } else {
@@ -478,10 +557,11 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       (rc = dalloc(h, &h->xrow, (size_t)h->nb * N * stdk::xrow_stride(h->W))) ||
       (rc = dalloc(h, &h->meta, T * (N + 1))) || (rc = dalloc(h, &h->aux, h->aux_host.size())) ||
       (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
-      (rc = dalloc(h, &h->partial, (size_t)h->W * stdk::pad4((int)P))) ||
+      (rc = dalloc(h, &h->partial, partial_floats(h))) || (h->R > 0 && (rc = dalloc(h, &h->B, (size_t)h->nB))) ||
       (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||
       (rc = dalloc(h, &h->bar, (size_t)h->W * stdk::kFlagStride)) ||
-      (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) || (rc = dalloc(h, &h->flag, 1)))
+      (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->nf, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) ||
+      (rc = dalloc(h, &h->flag, 1)))
     return bail(rc);
   for (int n = 0; n < N; ++n) {
     h->Jb[n] = (s.J[n] + 7) & ~7;
@@ -507,14 +587,14 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     const float* src_vals = p->vals;
     if (!o->inputs_on_device) {
       if ((rc = dalloc(h, &didx, T * N)) || (rc = dalloc(h, &dvals, T))) {
-        dfree(didx);
+        dfree(h, didx);
         return bail(rc);
       }
       h->device_bytes -= T * N * 4 + T * 4;
       if (hipMemcpyAsync(didx, p->idx, T * N * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
           hipMemcpyAsync(dvals, p->vals, T * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
-        dfree(didx);
-        dfree(dvals);
+        dfree(h, didx);
+        dfree(h, dvals);
         h->last_error = "copying the COO entries failed";
         return bail(STD_E_DEVICE);
       }
@@ -526,8 +606,8 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     if (e == hipSuccess) e = stdk::launch_pack_records(s, src_idx, src_vals, h->T, h->coo, h->flag, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    dfree(didx);
-    dfree(dvals);
+    dfree(h, didx);
+    dfree(h, dvals);
     if (e != hipSuccess) {
       h->last_error = std::string("packing the COO entries: ") + hipGetErrorString(e);
       return bail(STD_E_DEVICE);
@@ -556,7 +636,22 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       }
     }
     buf.assign((size_t)P, 0.f);
-    if (o->init_kind != STD_INIT_CALLER) {
+    if (h->R > 0) {
+      // Kruskal core: B(k) entries N(0, sd^2) with R sd^(2N) = 1/J_1, so that G
+      // = Kruskal(B) has the entry variance of the dense initialisation (or
+      // the paper's N(0.5, 0.1^2)); G is their product
+      std::vector<float> bb((size_t)h->nB, 0.f);
+      if (o->init_kind != STD_INIT_CALLER) {
+        const double sd = o->init_kind == STD_INIT_PAPER ? 0.1 : std::pow(1.0 / ((double)h->R * s.J[0]), 0.5 / N);
+        const double mu = o->init_kind == STD_INIT_PAPER ? 0.5 : 0.0;
+        for (auto& v : bb) v = (float)(mu + sd * rng.normal());
+      }
+      kruskal_product_host(s, h->R, bb.data(), buf);
+      if (hipMemcpy(h->B, bb.data(), bb.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        h->last_error = "copying the initial Kruskal factors failed";
+        return bail(STD_E_DEVICE);
+      }
+    } else if (o->init_kind != STD_INIT_CALLER) {
       const double sd = o->init_kind == STD_INIT_PAPER ? 0.1 : 1.0 / std::sqrt((double)s.J[0]);
       const double mu = o->init_kind == STD_INIT_PAPER ? 0.5 : 0.0;
       for (int64_t i = 0; i < P; ++i) buf[i] = (float)(mu + sd * rng.normal());
@@ -566,7 +661,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       return bail(STD_E_DEVICE);
     }
   }
-  if (hipMemsetAsync(h->partial, 0, (size_t)h->W * stdk::pad4((int)P) * 4, h->stream) != hipSuccess ||
+  if (hipMemsetAsync(h->partial, 0, partial_floats(h) * 4, h->stream) != hipSuccess ||
       refresh_bf16(h) != STD_OK) {
     h->last_error = "initialising device buffers failed";
     return bail(STD_E_DEVICE);
@@ -579,6 +674,19 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
 
 namespace {
 
+// STD_E_DIVERGED naming the first non-finite parameter the chain wrote
+// (stdk::nf_key of the record; all ones means none was recorded).
+int diverged_at(stdecomp_handle* h, int64_t epoch, unsigned long long key) {
+  const int64_t row = (int64_t)(key & 0x7FFFFFFFull);
+  const unsigned long long bp = key >> 31;
+  const int64_t b = (int64_t)(bp / 16);
+  const int ph = (int)(bp % 16);
+  std::string where = ph == 0 ? "core sub-step, core entry " + std::to_string(row)
+                              : "mode-" + std::to_string(ph - 1) + " sub-step, row " + std::to_string(row);
+  return fail(h, STD_E_DIVERGED, "non-finite parameters: first at epoch " + std::to_string(epoch) + ", minibatch " +
+                                     std::to_string(b) + (b == (1ll << 29) - 1 ? " or later" : "") + ", " + where);
+}
+
 // Minibatches [b0, b1) of epoch `epoch`, accumulated into *acc.
 int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecomp_epoch_stats* acc,
               std::vector<int>& nseg_host) {
@@ -590,6 +698,7 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
   }
   HIPCHK(h, hipEventRecord(h->ev[1], h->stream));
   HIPCHK(h, hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+  HIPCHK(h, hipMemsetAsync(h->nf, 0xFF, sizeof(unsigned long long), h->stream));
   stdk::ChainArgs a = chain_args(h);
   for (int64_t c0 = b0; c0 < b1; c0 += kBatchesPerLaunch) {
     a.b_begin = c0;
@@ -600,11 +709,14 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
   }
   HIPCHK(h, hipEventRecord(h->ev[2], h->stream));
   int err = 0;
+  unsigned long long nf = ~0ull;
   HIPCHK(h, hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&nf, h->nf, sizeof(nf), hipMemcpyDeviceToHost, h->stream));
   nseg_host.resize((size_t)h->nb * N);
   HIPCHK(h, hipMemcpyAsync(nseg_host.data(), h->nseg, nseg_host.size() * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (err) return fail(h, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+  if (nf != ~0ull) return diverged_at(h, epoch, nf);
   float t01 = 0, t12 = 0;
   HIPCHK(h, hipEventElapsedTime(&t01, h->ev[0], h->ev[1]));
   HIPCHK(h, hipEventElapsedTime(&t12, h->ev[1], h->ev[2]));
@@ -647,6 +759,7 @@ int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* s
   if (!h) return STD_E_STATE;
   if (n_epochs < 0) return fail(h, STD_E_INVAL, "n_epochs < 0");
   stdecomp_epoch_stats acc{};
+  acc.train_rmse = std::nan("");
   std::vector<int> nseg_host;
   for (int e = 0; e < n_epochs; ++e) {
     int rc = run_range(h, h->epoch, 0, h->nb, &acc, nseg_host);
@@ -654,8 +767,14 @@ int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* s
     acc.epochs_run++;
     h->epoch++;
   }
+  int rc = check_finite(h);
+  if (rc == STD_OK && h->train_rmse) {
+    stdecomp_loss_out lo{};
+    rc = stdecomp_loss(h, 0, nullptr, nullptr, 0, &lo);
+    acc.train_rmse = lo.rmse;
+  }
   if (st) *st = acc;
-  return check_finite(h);
+  return rc;
 }
 
 int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st) {
@@ -666,12 +785,12 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
   if (n_epochs < 0) return fail(h0, STD_E_INVAL, "n_epochs < 0");
   // one launch needs the same kernel variant, device and dtype, distinct
   // handles, and room for every chain's workgroups at once
-  bool one_launch = stdk::chain_multi_supported(h0->s);
+  bool one_launch = stdk::chain_multi_supported(h0->s) && h0->R == 0;
   int total_w = 0;
   size_t lds = 0;
   for (int i = 0; i < n && one_launch; ++i) {
     const stdecomp_handle* h = hs[i];
-    one_launch = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads &&
+    one_launch = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads && h->R == 0 &&
                  stdk::chain_variant(h->s) == stdk::chain_variant(h0->s) && (h->s.N == 3) == (h0->s.N == 3);
     for (int k = 0; k < i && one_launch; ++k) one_launch = hs[k] != h;
     total_w += h->W;
@@ -695,13 +814,25 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
     }
     max_nb = hs[i]->nb > max_nb ? hs[i]->nb : max_nb;
   }
-  stdk::ChainArgs* dargs = nullptr;
-  int* dmap = nullptr;
-  if (hipMalloc((void**)&dargs, sizeof(stdk::ChainArgs) * n) != hipSuccess ||
-      hipMalloc((void**)&dmap, sizeof(int) * map.size()) != hipSuccess) {
-    (void)hipFree(dargs);
-    return fail(h0, STD_E_NOMEM, "batched launch: device allocation failed");
+  // the launch's argument table and workgroup map live in a per-device
+  // workspace that grows on demand and is kept, so a call allocates only when
+  // it needs more than any call before it on that device
+  std::lock_guard<std::mutex> lock(g_batch_ws.mu);
+  BatchWorkspace::Dev& ws = g_batch_ws.dev[h0->device];
+  const size_t need = ((sizeof(stdk::ChainArgs) * n + 255) & ~(size_t)255) + sizeof(int) * map.size();
+  if (ws.bytes < need) {
+    if (ws.ptr) (void)hipFree(ws.ptr);
+    ws.ptr = nullptr;
+    ws.bytes = 0;
+    if (hipMalloc(&ws.ptr, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ws.ptr = nullptr;
+      return fail(h0, STD_E_NOMEM, "batched launch: device workspace allocation failed");
+    }
+    ws.bytes = need;
   }
+  stdk::ChainArgs* dargs = static_cast<stdk::ChainArgs*>(ws.ptr);
+  int* dmap = reinterpret_cast<int*>(static_cast<char*>(ws.ptr) + ((sizeof(stdk::ChainArgs) * n + 255) & ~(size_t)255));
   std::vector<stdk::ChainArgs> args((size_t)n);
   std::vector<stdecomp_epoch_stats> acc((size_t)n);
   int rc = STD_OK;
@@ -709,7 +840,8 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
     if (e != hipSuccess && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return e == hipSuccess;
   };
-  if (hipck(hipMemcpy(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice), "batched launch map")) {
+  if (hipck(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, h0->stream),
+            "batched launch map")) {
     for (int e = 0; e < n_epochs && rc == STD_OK; ++e) {
       for (int i = 0; i < n && rc == STD_OK; ++i) {
         stdecomp_handle* h = hs[i];
@@ -725,6 +857,7 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
           args[i].b_begin = c0 < h->nb ? c0 : h->nb;
           args[i].b_end = c0 + kBatchesPerLaunch < h->nb ? c0 + kBatchesPerLaunch : h->nb;
           hipck(hipMemsetAsync(h->err, 0, sizeof(int), h0->stream), "memset");
+          if (c0 == 0) hipck(hipMemsetAsync(h->nf, 0xFF, sizeof(unsigned long long), h0->stream), "memset");
           hipck(hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h0->stream), "memset");
         }
         hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
@@ -741,8 +874,15 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
       for (int i = 0; i < n && rc == STD_OK; ++i) {
         stdecomp_handle* h = hs[i];
         int err = 0;
-        hipck(hipMemcpy(&err, h->err, sizeof(int), hipMemcpyDeviceToHost), "error flag");
-        if (err) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+        unsigned long long nf = ~0ull;
+        hipck(hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h0->stream), "error flag");
+        hipck(hipMemcpyAsync(&nf, h->nf, sizeof(nf), hipMemcpyDeviceToHost, h0->stream), "non-finite record");
+        hipck(hipStreamSynchronize(h0->stream), "error flag");
+        if (err && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+        if (nf != ~0ull && rc == STD_OK) {
+          diverged_at(h, h->epoch, nf);
+          rc = fail(h0, STD_E_DIVERGED, "model " + std::to_string(i) + ": " + h->last_error);
+        }
         acc[i].epochs_run++;
         acc[i].updates += h->T;
         acc[i].minibatches += h->nb;
@@ -754,8 +894,6 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
       }
     }
   }
-  (void)hipFree(dargs);
-  (void)hipFree(dmap);
   if (rc) return rc;
   for (int i = 0; i < n; ++i) {
     if (st) st[i] = acc[i];
@@ -789,7 +927,7 @@ int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* o
   float* dout = out;
   if (!on_device) {
     if ((rc = dalloc(h, &dout, (size_t)q))) {
-      dfree(rec);
+      dfree(h, rec);
       return rc;
     }
     h->device_bytes -= (size_t)q * 4;
@@ -797,8 +935,8 @@ int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* o
   hipError_t e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(rec);
-  if (!on_device) dfree(dout);
+  dfree(h, rec);
+  if (!on_device) dfree(h, dout);
   if (e != hipSuccess) return hip_fail(h, e, "predict");
   return STD_OK;
 }
@@ -824,7 +962,7 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
                                    h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(sums, h->dscratch + 3 * nb, sizeof(sums), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(rec);
+  dfree(h, rec);
   if (e != hipSuccess) return hip_fail(h, e, "loss");
   double regA = 0.0, regG = 0.0, t = 0.0;
   for (int k = 0; k < h->s.N; ++k) {
@@ -894,6 +1032,42 @@ int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* 
   return refresh_bf16(h);
 }
 
+int stdecomp_get_kruskal(stdecomp_handle* h, float* const* B) {
+  if (!h) return STD_E_STATE;
+  if (h->R <= 0) return fail(h, STD_E_STATE, "the handle has a dense core (options.r_core = 0)");
+  if (!B) return fail(h, STD_E_INVAL, "NULL parameter pointer");
+  std::vector<float> buf((size_t)h->nB);
+  HIPCHK(h, hipMemcpyAsync(buf.data(), h->B, buf.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  size_t o = 0;
+  for (int n = 0; n < h->s.N; ++n) {
+    if (!B[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
+    const size_t len = (size_t)h->s.J[n] * h->R;
+    std::memcpy(B[n], buf.data() + o, len * 4);
+    o += len;
+  }
+  return STD_OK;
+}
+
+int stdecomp_set_kruskal(stdecomp_handle* h, const float* const* B) {
+  if (!h) return STD_E_STATE;
+  if (h->R <= 0) return fail(h, STD_E_STATE, "the handle has a dense core (options.r_core = 0)");
+  if (!B) return fail(h, STD_E_INVAL, "NULL parameter pointer");
+  std::vector<float> buf((size_t)h->nB), G;
+  size_t o = 0;
+  for (int n = 0; n < h->s.N; ++n) {
+    if (!B[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
+    const size_t len = (size_t)h->s.J[n] * h->R;
+    std::memcpy(buf.data() + o, B[n], len * 4);
+    o += len;
+  }
+  kruskal_product_host(h->s, h->R, buf.data(), G);
+  HIPCHK(h, hipMemcpyAsync(h->B, buf.data(), buf.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->G, G.data(), G.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return STD_OK;
+}
+
 int stdecomp_set_epoch(stdecomp_handle* h, int64_t e) {
   if (!h) return STD_E_STATE;
   if (e < 0) return fail(h, STD_E_INVAL, "negative epoch");
@@ -935,9 +1109,9 @@ int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, in
   int32_t *doff = nullptr, *drow = nullptr, *dn = nullptr;
   if ((rc = dalloc(h, &dperm, (size_t)h->T)) || (rc = dalloc(h, &doff, (size_t)m + 1)) ||
       (rc = dalloc(h, &drow, (size_t)m)) || (rc = dalloc(h, &dn, 1))) {
-    dfree(dperm);
-    dfree(doff);
-    dfree(drow);
+    dfree(h, dperm);
+    dfree(h, doff);
+    dfree(h, drow);
     return rc;
   }
   h->device_bytes -= (size_t)h->T * 8 + (size_t)(2 * m + 2) * 4;
@@ -953,22 +1127,33 @@ int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, in
   if (e == hipSuccess) e = hipMemcpyAsync(seg_off, doff, (size_t)(m + 1) * 4, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(seg_row, drow, (size_t)m * 4, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(dperm);
-  dfree(doff);
-  dfree(drow);
-  dfree(dn);
+  dfree(h, dperm);
+  dfree(h, doff);
+  dfree(h, drow);
+  dfree(h, dn);
   if (e != hipSuccess) return hip_fail(h, e, "debug_schedule");
   for (int q = 0; q < m; ++q) sigma[q] = sig[q];
   *m_out = m;
   return STD_OK;
 }
 
-int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out) {
+int stdecomp_sample_order(int64_t T, uint64_t seed, int64_t epoch, int64_t* out, int32_t out_on_device,
+                          void* stream) {
   if (T < 1 || epoch < 0 || !out) return STD_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (out_on_device) {
+    hipError_t e = stdk::launch_perm_only(T, seed, epoch, out, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e == hipSuccess ? STD_OK : STD_E_DEVICE;
+  }
   int64_t* d = nullptr;
-  if (hipMalloc((void**)&d, (size_t)T * 8) != hipSuccess) return STD_E_NOMEM;
-  hipError_t e = stdk::launch_perm_only(T, seed, epoch, d, nullptr);
-  if (e == hipSuccess) e = hipMemcpy(out, d, (size_t)T * 8, hipMemcpyDeviceToHost);
+  if (hipMalloc((void**)&d, (size_t)T * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    return STD_E_NOMEM;
+  }
+  hipError_t e = stdk::launch_perm_only(T, seed, epoch, d, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, (size_t)T * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d);
   return e == hipSuccess ? STD_OK : STD_E_DEVICE;
 }

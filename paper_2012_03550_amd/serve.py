@@ -49,9 +49,11 @@ class Job:
 
 
 class Server:
-    def __init__(self, hbm_budget, max_workgroups=256, chunk=128, dtype="f32", lr=0.01, lam=0.01, on_finish=None):
+    def __init__(self, hbm_budget, max_workgroups=256, chunk=128, dtype="f32", lr=0.01, lam=0.01, on_finish=None,
+                 on_epoch=None):
         self.budget = hbm_budget
         self.on_finish = on_finish  # called with a finished job while its handle is still open
+        self.on_epoch = on_epoch    # called with a job after each of its epochs (handle open)
         self.max_wgs = max_workgroups
         self.chunk = chunk
         self.dtype = dtype
@@ -98,6 +100,8 @@ class Server:
                         for j in batch:
                             j.done_epochs += 1
                             self.updates += j.idx.shape[1]
+                            if self.on_epoch is not None:
+                                self.on_epoch(j)
                         if between is not None:
                             between()
                     batch, wgs = [], 0
