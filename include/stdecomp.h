@@ -168,6 +168,21 @@ int stdecomp_run_minibatches(stdecomp_handle* h, int64_t epoch, int64_t b_begin,
  * out of range gives STD_E_INVAL and writes nothing. */
 int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* out, int32_t on_device);
 
+/* stdecomp_predict for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results as stdecomp_predict, but the
+ * packed queries (and, for host buffers, the staged indices and outputs) live
+ * in a fixed 16 MiB device array of the library, one per device, resolved at
+ * stdecomp_init; the call allocates nothing.  The caller still owns idx and
+ * out (both host or both device memory, as in stdecomp_predict).  Limit: the
+ * queries must fit the array, pad256(4 q (N + 1)) bytes with device buffers
+ * plus pad256(4 q N) + 4 q with host buffers (e.g. 1048576 queries of a
+ * three-mode model from device memory, 524288 from host memory); a larger q
+ * gives STD_E_INVAL and writes nothing.  Every handle on a device shares that
+ * device's array: calls that overlap on one device (from several host
+ * threads) race. */
+int stdecomp_predict_noalloc(stdecomp_handle* h, int64_t q, const int32_t* idx, float* out, int32_t on_device);
+
 /* RMSE, MAE and SSE over n entries (host or device, SoA idx [N][n], vals
  * [n]); idx == NULL and vals == NULL evaluates the training set Omega. */
 int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float* vals, int32_t on_device,

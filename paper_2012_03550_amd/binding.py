@@ -69,6 +69,8 @@ SIGNATURES = {
     "stdecomp_run_minibatches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                                 ctypes.POINTER(EpochStats)]),
     "stdecomp_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "stdecomp_predict_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_int32]),
     "stdecomp_loss": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.POINTER(LossOut)]),
     "stdecomp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
@@ -291,6 +293,26 @@ class Stdecomp:
         out = np.empty(idx.shape[1], np.float32)
         self._check(load().stdecomp_predict(self._h, idx.shape[1], _ptr(idx), _ptr(out), 0), "stdecomp_predict")
         return out
+
+    def predict_noalloc(self, idx, out=None):
+        """predict() through the entry point that allocates nothing (the
+        library's fixed scratch array).  Host numpy indices give a numpy
+        result; device indices write into ``out`` (a float32 device tensor of
+        q values, allocated here if not given)."""
+        L = load()
+        if _is_device(idx):
+            import torch
+            idx = _dev_coo(idx)
+            if out is None:
+                out = torch.empty(idx.shape[1], dtype=torch.float32, device=idx.device)
+            self._check(L.stdecomp_predict_noalloc(self._h, idx.shape[1], _ptr(idx), _ptr(out), 1),
+                        "stdecomp_predict_noalloc")
+            return out
+        idx = np.ascontiguousarray(idx, np.int32)
+        res = np.empty(idx.shape[1], np.float32)
+        self._check(L.stdecomp_predict_noalloc(self._h, idx.shape[1], _ptr(idx), _ptr(res), 0),
+                    "stdecomp_predict_noalloc")
+        return res
 
     def loss(self, idx=None, vals=None):
         out = LossOut()

@@ -161,6 +161,17 @@ __global__ void k_nonfinite(const float* __restrict__ p, int64_t n, int* flag) {
     if (!isfinite(p[i])) *flag = 1;
 }
 
+// p[0..n) = v (a kernel, not a memset node, so that captured graphs replay it).
+__global__ void k_fill_i32(int* p, int v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_count_nonfinite(const float* p, int64_t n, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, n, flag);
   return hipGetLastError();

@@ -182,6 +182,7 @@ hipError_t launch_loss(const Shape& s, const uint32_t* rec, int64_t n, FactorPtr
                        double* block_out, int nblocks, double* out3, hipStream_t st);
 hipError_t launch_sumsq(const float* p, int64_t n, double* block_out, int nblocks, hipStream_t st);
 hipError_t launch_count_nonfinite(const float* p, int64_t n, int* flag, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
 // rows x cols FP32 (row stride sstride) -> BF16 (row stride dstride), round to nearest even
 hipError_t launch_rows_to_bf16(const float* src, int sstride, uint16_t* dst, int dstride, int64_t rows, int cols,

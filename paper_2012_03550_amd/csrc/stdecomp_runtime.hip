@@ -68,6 +68,14 @@ struct stdecomp_handle {
   bool train_rmse = false;  // epoch stats carry the training RMSE
 };
 
+// Scratch memory of stdecomp_predict_noalloc: a file-scope device array (one
+// copy on every device the library runs on, held until the process ends).
+// Host code never uses its name as an address: stdecomp_init resolves the
+// device address once per device (hipGetSymbolAddress with that device
+// current) and the entry point passes that address to the kernels and copies.
+static constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 int fail(stdecomp_handle* h, int code, const std::string& msg) {
@@ -97,6 +105,41 @@ struct BatchWorkspace {
   Dev dev[64];
 };
 BatchWorkspace g_batch_ws;
+
+// Per-device address of the scratch array (filled by resolve_scratch).
+struct ScratchTable {
+  std::mutex mu;
+  void* ptr[64] = {};
+};
+ScratchTable g_scratch;
+
+// Resolve the scratch array's address on the current device (once per device).
+int resolve_scratch(stdecomp_handle* h) {
+  std::lock_guard<std::mutex> lock(g_scratch.mu);
+  if (h->device < 0 || h->device >= 64) return fail(h, STD_E_DEVICE, "device ordinal out of range");
+  if (g_scratch.ptr[h->device]) return STD_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(h, STD_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+  }
+  g_scratch.ptr[h->device] = p;
+  return STD_OK;
+}
+
+int64_t noalloc_max_queries(const stdecomp_handle* h, int32_t on_device) {
+  // largest q with pad256(q R 4) + [pad256(q N 4) + q 4] <= the scratch size
+  const int64_t per = (int64_t)h->s.R * 4 + (on_device ? 0 : (int64_t)h->s.N * 4 + 4);
+  int64_t q = (int64_t)kNoAllocScratchBytes / per;
+  while (q > 0) {
+    const size_t need = (((size_t)q * h->s.R * 4 + 255) & ~(size_t)255) +
+                        (on_device ? 0 : (((size_t)q * h->s.N * 4 + 255) & ~(size_t)255) + (size_t)q * 4);
+    if (need <= kNoAllocScratchBytes) break;
+    --q;
+  }
+  return q;
+}
 
 constexpr int kBatchesPerLaunch = 2048;  // bounds the duration of one chain launch
 constexpr long long kSpinLimit = 1ll << 24;
@@ -549,6 +592,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     }
   int rc = configure_chain(h, o->chain_chunk);
   if (rc) return bail(rc);
+  if ((rc = resolve_scratch(h))) return bail(rc);
 
   // device memory
   const size_t T = (size_t)h->T;
@@ -938,6 +982,51 @@ int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* o
   dfree(h, rec);
   if (!on_device) dfree(h, dout);
   if (e != hipSuccess) return hip_fail(h, e, "predict");
+  return STD_OK;
+}
+
+int stdecomp_predict_noalloc(stdecomp_handle* h, int64_t q, const int32_t* idx, float* out, int32_t on_device) {
+  if (!h) return STD_E_STATE;
+  if (q < 0 || (q > 0 && (!idx || !out))) return fail(h, STD_E_INVAL, "bad predict arguments");
+  if (q == 0) return STD_OK;
+  const int N = h->s.N;
+  const size_t rec_bytes = ((size_t)q * h->s.R * 4 + 255) & ~(size_t)255;
+  const size_t idx_bytes = on_device ? 0 : (((size_t)q * N * 4 + 255) & ~(size_t)255);
+  const size_t out_bytes = on_device ? 0 : (size_t)q * 4;
+  if (rec_bytes + idx_bytes + out_bytes > kNoAllocScratchBytes)
+    return fail(h, STD_E_INVAL, "stdecomp_predict_noalloc: " + std::to_string(q) + " queries need " +
+                                    std::to_string(rec_bytes + idx_bytes + out_bytes) + " bytes of scratch, more than " +
+                                    std::to_string(kNoAllocScratchBytes) + " (at most " +
+                                    std::to_string(noalloc_max_queries(h, on_device)) + " queries)");
+  void* base = g_scratch.ptr[h->device];
+  if (!base) return fail(h, STD_E_STATE, "scratch address not resolved for this device");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, STD_E_DEVICE, "hipSetDevice failed");
+  uint32_t* rec = static_cast<uint32_t*>(base);
+  const int32_t* didx = idx;
+  float* dout = out;
+  if (!on_device) {
+    // host indices are range-checked here, as stdecomp_predict does, then staged in scratch
+    for (int k = 0; k < N; ++k)
+      for (int64_t t = 0; t < q; ++t) {
+        const int32_t v = idx[(int64_t)k * q + t];
+        if (v < 0 || v >= h->s.I[k]) return fail(h, STD_E_INVAL, "index out of range");
+      }
+    int32_t* sidx = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(base) + rec_bytes);
+    HIPCHK(h, hipMemcpyAsync(sidx, idx, (size_t)q * N * 4, hipMemcpyHostToDevice, h->stream));
+    didx = sidx;
+    dout = reinterpret_cast<float*>(static_cast<unsigned char*>(base) + rec_bytes + idx_bytes);
+  }
+  int bad = 0;
+  hipError_t e = stdk::launch_fill_i32(h->flag, 0, 1, h->stream);
+  if (e == hipSuccess) e = stdk::launch_pack_records(h->s, didx, nullptr, q, rec, h->flag, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "predict_noalloc: packing entries");
+  if (bad) return fail(h, STD_E_INVAL, "index out of range");
+  e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->stream);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "predict_noalloc");
   return STD_OK;
 }
 
