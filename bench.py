@@ -52,13 +52,16 @@ def main():
                          "(0: skip; the oracle runs them in a thread beside the GPU steps)")
     ap.add_argument("--traffic-json", default=None,
                     help="(c2) counter record of the chain (default: profiles/chain_traffic_ratings_zipf[_bf16].json)")
-    ap.add_argument("--duration", type=float, default=10.0, help="(c5) seconds of job arrivals")
+    ap.add_argument("--duration", type=float, default=3.0, help="(c5) seconds of job arrivals")
     ap.add_argument("--config", default="c3", choices=["c2", "c3", "c4", "c5", "ranks"],
                     help="c3 (default): 4-order planted power-law tensor, FP32 vs BF16; c2: Netflix-shaped ratings; "
                          "c4: 64 independent planted tensors, batched launches vs one model at a time; "
                          "c5: serving loop (Poisson jobs and queries), p50/p99 latency; "
                          "ranks: core-rank sweep J = 4..24 on a ratings tensor")
     ap.add_argument("--dtypes", default="f32,bf16", help="(c3) precisions to run, the first is the headline")
+    ap.add_argument("--rcore", type=int, default=0,
+                    help="(c3) 0: dense core; R > 0: the paper's Kruskal core of rank R (the oracle prefix then "
+                         "defaults to 2 minibatches, 1 of them timed)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -209,8 +212,9 @@ def run_c3(args):
     log("generated %d training / %d held-out entries in %.1fs" % (wl.nnz, wl.test_vals.size, time.time() - t))
     M, lr, lam, sample = 8192, 0.05, 1e-4, 200_000
     seed_s, seed_i = 3003, 2003
-    prefix = max(0, args.prefix)
-    cpu_batches = 48 if args.cpu_batches < 0 else args.cpu_batches
+    R = max(0, args.rcore)
+    prefix = max(0, args.prefix) if (R == 0 or args.prefix != 200) else 2
+    cpu_batches = (48 if R == 0 else 1) if args.cpu_batches < 0 else args.cpu_batches
     cpu_batches = min(cpu_batches, prefix) if prefix else cpu_batches
     dtypes = [d for d in args.dtypes.split(",") if d]
     test_idx = torch.from_numpy(wl.test_idx).cuda()
@@ -218,26 +222,30 @@ def run_c3(args):
     s_idx = np.ascontiguousarray(wl.test_idx[:, :sample])
     s_vals = np.ascontiguousarray(wl.test_vals[:sample])
     res, orc = {}, {}
-    A0 = G0 = None
+    A0 = G0 = B0 = None
     worker = None
     for dtype in dtypes:
         h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
-                             lam_factor=lam, lam_core=lam, seed_sample=seed_s, seed_init=seed_i, dtype=dtype)
+                             lam_factor=lam, lam_core=lam, seed_sample=seed_s, seed_init=seed_i, dtype=dtype,
+                             r_core=R)
         if A0 is None:
             A0, G0 = h.get_params()
+            B0 = h.get_kruskal() if R else None
             if prefix > 0 or cpu_batches > 0:
                 worker = threading.Thread(target=oracle_prefix, daemon=True,
                                           args=(wl, A0, G0, M, lr, lam, seed_s, max(prefix, cpu_batches),
-                                                cpu_batches, s_idx, s_vals, orc))
+                                                cpu_batches, s_idx, s_vals, orc, B0))
                 worker.start()
         info = h.info()
         log("c3 %s chain" % dtype, info)
         r = {"chain_workgroups": info["workgroups"], "chain_chunk": info["chunk"]}
         if prefix > 0:
             h.run_minibatches(0, 0, prefix)
-            r["prefix_params"] = h.get_params()
+            r["prefix_params"] = h.get_params() + ((h.get_kruskal(),) if R else ())
             r["prefix_heldout_rmse_sample"] = h.loss(s_idx, s_vals)["rmse"]
         h.set_params(A0, G0)
+        if R:
+            h.set_kruskal(B0)
         A1, G1 = h.get_params()
         if not (all(np.array_equal(a, b) for a, b in zip(A0, A1)) and np.array_equal(G0, G1)):
             raise RuntimeError("c3 %s: parameters read back after set_params differ from those set" % dtype)
@@ -276,9 +284,12 @@ def run_c3(args):
         precision = {"prefix_minibatches": prefix, "heldout_sample": sample,
                      "rmse_oracle_f64": round(orc["rmse"], 9)}
         for dtype in dtypes:
-            Ag, Gg = res[dtype].pop("prefix_params")
+            pp = res[dtype].pop("prefix_params")
+            Ag, Gg = pp[0], pp[1]
             rg = res[dtype].pop("prefix_heldout_rmse_sample")
             errs = [rel_err(Ag[n], orc["A"][n]) for n in range(len(wl.dims))] + [rel_err(Gg, orc["G"])]
+            if R:
+                errs += [rel_err(pp[2][n], orc["B"][n]) for n in range(len(wl.dims))]
             precision[dtype] = {"rmse": round(rg, 9), "rmse_rel_gap": (rg - orc["rmse"]) / orc["rmse"],
                                 "params_max_rel_err": max(errs)}
     else:
@@ -300,8 +311,9 @@ def run_c3(args):
            "dtype": dtypes[0], "data": "synthetic",
            "config": {"workload": "planted_powerlaw 100000x100000x1000x100, %d entries (Zipf 1.2 on modes 1-2, "
                                   "uniform on 3-4), planted rank 8^4 + N(0,0.05^2), 10%% held out; J=(8,8,8,8), "
-                                  "M=8192, lr=0.05, lambda=1e-4; step = 1 epoch + held-out RMSE" % nnz,
-                      "train_entries": int(wl.nnz), "batch": M, "chain_workgroups": head["chain_workgroups"],
+                                  "M=8192, lr=0.05, lambda=1e-4%s; step = 1 epoch + held-out RMSE" % (
+                                      nnz, "; Kruskal core R=%d" % R if R else ""),
+                      "train_entries": int(wl.nnz), "batch": M, "r_core": R, "chain_workgroups": head["chain_workgroups"],
                       "chain_chunk": head["chain_chunk"]},
            "heldout_rmse": head["heldout_rmse_per_step"][-1] if head["heldout_rmse_per_step"] else None,
            "roofline": head["roofline"], "precision": precision, "cpu_baseline": cpu}
@@ -310,7 +322,7 @@ def run_c3(args):
     print(json.dumps(out), flush=True)
 
 
-def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out):
+def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out, B0=None):
     """The FP64 oracle on minibatches [0, nb) of epoch 0 from (A0, G0): the
     entries of those minibatches are taken in the oracle's own epoch order
     and run as a tensor of nb * M entries in identity order (the same
@@ -324,7 +336,11 @@ def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out
     idx = np.ascontiguousarray(wl.train_idx[:, order])
     vals = np.ascontiguousarray(wl.train_vals[order])
     del order
-    ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    if B0 is None:
+        ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+    else:  # the Kruskal core: the model's core is the product of B0
+        ref = oracle.KruskalModel(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0],
+                                  [b.astype(np.float64) for b in B0])
     cut = min(idx.shape[1], nb_timed * M)
     log("oracle: running %d minibatches of epoch 0 (%d timed)" % (nb, nb_timed))
     t = time.perf_counter()
@@ -337,6 +353,8 @@ def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out
     out["rmse"] = ref.loss(s_idx, s_vals)["rmse"]
     out["A"] = [a.copy() for a in ref.A]
     out["G"] = ref.G.copy()
+    if B0 is not None:
+        out["B"] = [b.copy() for b in ref.B]
     log("oracle: %d minibatches in %.1fs (first %d in %.1fs), sample held-out RMSE %.6f" % (
         nb, time.perf_counter() - t, nb_timed, out["seconds"], out["rmse"]))
 
@@ -375,10 +393,12 @@ def chain_roofline(acc, dtype, traffic, lat):
 def run_c4(args):
     """64 independent three-mode tensors (mode sizes 10^U(3,6), 10^U(4,7)
     entries, uniform indices, equal ranks from {4, 8, 16}, planted models plus
-    N(0, 0.01^2) noise); M = 1024, lr = lambda = 0.01, 128-entry chunks.
-    Models of one rank share a kernel and run as one batched launch per
-    epoch; the comparison runs every model alone.  value = all models'
-    nonzero-updates per second of batched epochs."""
+    N(0, 0.01^2) noise); M = 1024, lr = lambda = 0.01, 128-entry chunks (8
+    workgroups per chain).  One batched call per epoch runs all 64 chains in
+    one cooperative launch: slots of 8 workgroups, as many as the device
+    holds, each running a list of chains balanced on the host (longest
+    first).  The comparison runs every model alone, one after another.
+    value = all models' nonzero-updates per second of batched epochs."""
     import numpy as np
     import torch
     from oracle import oracle
@@ -396,18 +416,20 @@ def run_c4(args):
         hs = [binding.Stdecomp(w.dims, w.ranks, w.train_idx, w.train_vals, batch=M, lr_factor=lr, lr_core=lr,
                                lam_factor=lam, lam_core=lam, seed_sample=3004 + k, seed_init=2004 + k, chunk=chunk,
                                dtype=dtype) for k, w in enumerate(wls)]
-        groups = {}
-        for h, w in zip(hs, wls):
-            groups.setdefault(w.ranks[0], []).append(h)
-        for g in groups.values():  # warm-up epoch
-            binding.epoch_batched(g, 1)
+        for _ in range(max(1, args.warmup)):
+            binding.epoch_batched(hs, 1)
         torch.cuda.synchronize()
+        acc = {"chain_seconds": 0.0, "chain_launches": 0, "flops_alg": 0.0, "bytes_alg": 0.0}
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            for g in groups.values():
-                binding.epoch_batched(g, 1)
+            st = binding.epoch_batched(hs, 1)
+            acc["chain_seconds"] += st[0]["chain_seconds"]
+            acc["chain_launches"] += st[0]["chain_launches"]
+            acc["flops_alg"] += sum(x["flops_alg"] for x in st)
+            acc["bytes_alg"] += sum(x["bytes_alg"] for x in st)
         torch.cuda.synchronize()
-        batched = total * args.steps / (time.perf_counter() - t0)
+        wall = time.perf_counter() - t0
+        batched = total * args.steps / wall
         t0 = time.perf_counter()
         for h in hs:
             h.epoch(1)
@@ -417,8 +439,11 @@ def run_c4(args):
         for h in hs:
             h.close()
         log("c4 %s: batched %.3e updates/s, one model at a time %.3e" % (dtype, batched, alone))
+        Js = sorted({w.ranks[0] for w in wls})
         res[dtype] = {"updates_per_s": round(batched, 1), "alone_updates_per_s": round(alone, 1),
-                      "speedup": round(batched / alone, 3), "groups": {str(j): len(g) for j, g in groups.items()},
+                      "speedup": round(batched / alone, 3), "ms_per_step": round(wall / args.steps * 1e3, 3),
+                      "ranks": {str(j): sum(1 for w in wls if w.ranks[0] == j) for j in Js},
+                      "roofline": chain_roofline(acc, dtype, None, None),
                       "train_rmse_max": round(max(rmse), 6), "train_rmse_median": round(float(np.median(rmse)), 6)}
     # CPU baseline: the oracle over the four smallest tensors, one epoch each
     oracle.build()
@@ -433,12 +458,13 @@ def run_c4(args):
         upd += w.nnz
     dt = time.perf_counter() - t
     out = {"metric": METRIC, "value": res["f32"]["updates_per_s"],
-           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True,
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup),
+           "ms_per_step": res["f32"]["ms_per_step"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "64 planted three-mode tensors, mode sizes 10^U(3,6), 10^U(4,7) entries, J from "
-                                  "{4,8,16}, M=1024, lr=lambda=0.01; step = 1 epoch of every tensor, batched per rank",
+                                  "{4,8,16}, M=1024, lr=lambda=0.01; step = 1 epoch of every tensor, one batched launch",
                       "tensors": len(wls), "entries": int(total), "batch": M, "chunk": chunk},
-           "f32": res["f32"], "bf16": res["bf16"],
+           "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"],
            "cpu_baseline": dict({"value": round(upd / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
                                  "sample": "one epoch of each of the 4 smallest tensors (%d updates), FP64 C, one "
                                            "thread, from the host initialiser's own draw (a timing sample)" % upd},
@@ -448,13 +474,19 @@ def run_c4(args):
 
 def run_c5(args):
     """Serving: decomposition jobs arrive by a Poisson process (20/s for
-    --duration seconds), each a planted tensor of order 3 or 4 with
-    10^U(4,6) entries, mode sizes 10^U(3,5), equal ranks from {4, 8, 16}
-    (order 4: {4, 8}), N(0, 0.01^2) noise, 5 epochs, M = 1024; completion
-    queries (random index tuples of a resident model) arrive at 10^5/s.
-    Jobs are admitted by device footprint and advance one epoch per round,
-    jobs with the same kernel in one batched launch; queries are answered
-    between rounds.  value = nonzero-updates/s over the whole run."""
+    --duration seconds), each a planted tensor of order 3, 4 or 5 with
+    10^U(4,8) entries, mode sizes 10^U(3,6), equal ranks J uniform in 4..16,
+    N(0, 0.01^2) noise, 5 epochs, M = 1024; completion queries (random index
+    tuples of a resident model) arrive at 10^5/s.  A background thread admits
+    jobs by device footprint (a job whose core and tables exceed one
+    workgroup's LDS is rejected with the library's reason) and runs rounds of
+    one epoch of every resident job, batched launches over the device's
+    slots; the main thread submits arrivals and answers the queries that have
+    arrived, every 2 ms, on the handles' query streams beside the training
+    launches.  value = nonzero-updates/s over the whole run; offered load =
+    the arriving jobs' updates (entries x epochs) per second of arrivals."""
+    import threading
+
     import numpy as np
     import torch
     from paper_2012_03550_amd import serve, synth
@@ -469,65 +501,78 @@ def run_c5(args):
         t += rng.exponential(1 / 20.0)
         if t > D:
             break
-        N = int(rng.choice([3, 4]))
-        J = int(rng.choice([4, 8, 16] if N == 3 else [4, 8]))
-        dims = tuple(int(10 ** rng.uniform(3, 5)) for _ in range(N))
-        nnz = int(10 ** rng.uniform(4, 6))
+        N = int(rng.choice([3, 4, 5]))
+        J = int(rng.integers(4, 17))
+        dims = tuple(int(10 ** rng.uniform(3, 6)) for _ in range(N))
+        nnz = int(10 ** rng.uniform(4, 8))
         idx = np.stack([synth.uniform_indices(rng, I, nnz) for I in dims])
         A, G = synth.planted_model(rng, dims, (J,) * N)
-        clean = synth.evaluate_planted_device(A, G, (J,) * N, idx, "cuda")
+        P = J ** N
+        if P <= 1 << 14:  # (chunks of entries sized so the contraction's product stays near 1 GB)
+            clean = synth.evaluate_planted_device(A, G, (J,) * N, idx, "cuda", chunk=max(1024, (1 << 27) // P))
+        else:  # a core this large does not fit one workgroup's LDS: the library rejects the job at admission
+            clean = np.zeros(nnz)
         vals = (clean + rng.standard_normal(nnz) * 0.01).astype(np.float32)
         jobs.append(serve.Job(len(jobs), t, dims, (J,) * N, idx, vals, epochs=5, seed=3005 + len(jobs)))
     qarr = np.sort(rng.uniform(0.0, D, rng.poisson(1e5 * D)))
-    log("trace: %d jobs (%d entries), %d queries; generated in %.1fs" %
-        (len(jobs), sum(j.idx.shape[1] for j in jobs), qarr.size, time.time() - t_gen))
-    srv = serve.Server(hbm_budget=100 << 30, dtype=args.dtype)
+    offered = sum(j.idx.shape[1] * j.epochs for j in jobs) / D
+    log("trace: %d jobs (%d entries), %d queries; generated in %.1fs; offered %.3e updates/s" %
+        (len(jobs), sum(j.idx.shape[1] for j in jobs), qarr.size, time.time() - t_gen, offered))
+    srv = serve.Server(hbm_budget=200 << 30, chunk=0, dtype=args.dtype)
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0  # noqa: E731
-    qlat = []
-    qpos = [0]
-
-    def answer_queries():  # every query that has arrived, if a model is resident
-        hi = int(np.searchsorted(qarr, clock(), side="right"))
-        if hi > qpos[0] and srv.answer(hi - qpos[0], rng):
-            done = clock()
-            qlat.extend((done - qarr[qpos[0]:hi]).tolist())
-            qpos[0] = hi
-
-    ji = 0
-    rounds = 0
-    while ji < len(jobs) or srv.pending or srv.active:
+    stop = threading.Event()
+    trainer = threading.Thread(target=srv.run, args=(clock, stop), daemon=True)
+    trainer.start()
+    qlat, qpos, ji, dropped = [], 0, 0, 0
+    last_log = 0.0
+    while True:
         now = clock()
         while ji < len(jobs) and jobs[ji].arrival <= now:
             srv.submit(jobs[ji])
             ji += 1
-        srv.admit(now)
-        if srv.active:
-            srv.round(clock, answer_queries)
-            rounds += 1
-        elif ji < len(jobs):
-            time.sleep(max(0.0, jobs[ji].arrival - clock()))
-        answer_queries()
-        if rounds and rounds % 50 == 0:
-            log("round %d: t=%.1fs, %d done, %d active, %d waiting" % (rounds, clock(), len(srv.done),
-                                                                    len(srv.active), len(srv.pending)))
-        if clock() > D + 600:
-            log("stopping: the run exceeded its time limit")
+        if ji == len(jobs):
+            stop.set()
+        hi = int(np.searchsorted(qarr, now, side="right"))
+        if hi > qpos:
+            got = srv.answer(hi - qpos, rng)
+            if got:
+                done = clock()
+                qlat.extend((done - qarr[qpos:hi]).tolist())
+                dropped += (hi - qpos) - got
+                qpos = hi
+        if now - last_log > 10.0:
+            last_log = now
+            log("t=%.1fs: %d done, %d active, %d waiting, %d rejected, %d queries answered" % (
+                now, len(srv.done), len(srv.active), len(srv.pending), len(srv.rejected), len(qlat)))
+        if stop.is_set() and not trainer.is_alive():
             break
+        if now > D + 900:
+            log("stopping: the run exceeded its time limit")
+            stop.set()
+            break
+        time.sleep(0.002)
+    trainer.join(timeout=60)
     wall = clock()
     jl = [j.finished - j.arrival for j in srv.done]
+    reasons = {}
+    for j in srv.rejected:
+        reasons[j.rejected.split(":")[-1].strip()[:80]] = reasons.get(j.rejected.split(":")[-1].strip()[:80], 0) + 1
     out = {"metric": METRIC, "value": round(srv.updates / wall, 1),
-           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": rounds, "warmup": 0, "higher_is_better": True,
+           "unit": "nonzero-updates/s", "n_gpus": 1, "steps": srv.rounds, "warmup": 0, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-           "config": {"workload": "serving: Poisson jobs 20/s for %gs (order 3-4, 10^U(4,6) entries, J in {4,8,16}, "
-                                  "5 epochs, M=1024) + completion queries 1e5/s" % D,
+           "config": {"workload": "serving: Poisson jobs 20/s for %gs (order 3-5, 10^U(4,8) entries, mode sizes "
+                                  "10^U(3,6), J uniform 4..16, 5 epochs, M=1024) + completion queries 1e5/s" % D,
                       "jobs": len(jobs), "queries": int(qarr.size)},
-           "serve": {"jobs_done": len(srv.done), "job_latency_s_p50": percentile_or_none(jl, 50),
-                     "job_latency_s_p99": percentile_or_none(jl, 99),
-                     "queries_answered": len(qlat), "query_latency_ms_p50": ms_or_none(percentile_or_none(qlat, 50)),
+           "serve": {"jobs_done": len(srv.done), "jobs_rejected": len(srv.rejected), "rejected_reasons": reasons,
+                     "job_latency_s_p50": percentile_or_none(jl, 50), "job_latency_s_p99": percentile_or_none(jl, 99),
+                     "queries_answered": len(qlat), "queries_dropped": dropped,
+                     "query_latency_ms_p50": ms_or_none(percentile_or_none(qlat, 50)),
                      "query_latency_ms_p99": ms_or_none(percentile_or_none(qlat, 99)),
+                     "offered_updates_per_s": round(offered, 1),
+                     "achieved_updates_per_s": round(srv.updates / wall, 1),
                      "job_train_rmse_median": percentile_or_none([j.rmse for j in srv.done], 50),
-                     "wall_s": round(wall, 3), "rounds": rounds}}
+                     "wall_s": round(wall, 3), "rounds": srv.rounds}}
     print(json.dumps(out), flush=True)
 
 

@@ -18,10 +18,17 @@
  *    j_1 fastest: G[j_1 + J_1*(j_2 + J_2*(...))] (Definitions "Tensor
  *    Unfolding" and "Vectorization" applied to the core).
  *  - Every function returns STD_OK (0) or a negative STD_E_* code and throws
- *    no C++ exception.  A handle is used by one host thread at a time;
- *    distinct handles are independent.
- *  - All device work runs on the handle's HIP stream; every call returns
- *    after that work has finished (the calls are synchronous).
+ *    no C++ exception.  A handle is used by one host thread at a time, with
+ *    one exception: stdecomp_predict / stdecomp_predict_noalloc run on the
+ *    handle's own query stream and may be called from one other thread while
+ *    a training call (stdecomp_epoch, stdecomp_run_minibatches,
+ *    stdecomp_epoch_batched) runs on the handle; they then read the
+ *    parameters as the chain updates them (every value is the one before or
+ *    after an update) and change nothing the training reads.  Distinct
+ *    handles are independent.
+ *  - Device work runs on the handle's HIP stream (predictions: on a second
+ *    stream of the handle, created with the same default priority); every
+ *    call returns after its work has finished (the calls are synchronous).
  */
 #ifndef STDECOMP_H
 #define STDECOMP_H
@@ -114,7 +121,9 @@ typedef struct {
   double chain_seconds;    /* part spent in the minibatch chain */
   int64_t chain_launches;  /* chain kernel launches */
   double bytes_alg;        /* algorithmic bytes of the chain (COO read + rows read/written + core) */
-  double flops_alg;        /* algorithmic flops of the chain, (2N+4) * prod(J) per update */
+  double flops_alg;        /* algorithmic flops of the chain: (2N+4) prod(J) per update with a dense
+                              core; with the Kruskal core 2N prod(J) plus, per mode n, the row of
+                              [W | x] and its Gram matrix, 2R sum_{k!=n} J_k + R J_n + (R J_n + 1)(R J_n + 2) */
   double train_rmse;       /* RMSE over Omega after the last epoch (Section "Experimental
                               Settings"), FP64 sums; NaN unless options.report_train_rmse */
 } stdecomp_epoch_stats;
@@ -136,7 +145,8 @@ typedef struct {
   int64_t lds_bytes;       /* LDS per chain workgroup */
   int64_t device_bytes;    /* device memory held by the handle */
   int64_t minibatches;     /* per epoch: ceil(T / M) */
-  int64_t epoch;           /* next epoch index */
+  int64_t epoch;           /* next epoch index (the current one inside stdecomp_step_batched's windows) */
+  int64_t cursor;          /* next minibatch of that epoch for stdecomp_step_batched (0 at an epoch start) */
 } stdecomp_info_out;
 
 /* Fill *o with the defaults: M = 256, gamma = lambda = 0.01, seeds 0, scaled
@@ -230,6 +240,21 @@ int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, in
  * handle; otherwise as stdecomp_epoch (reported on hs[0]). */
 int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st);
 
+/* Continuous batching: advance each of n models by up to max_minibatches
+ * minibatches of its current epoch, from where its previous call of this kind
+ * stopped (the cursor of stdecomp_info_out), in the launches of
+ * stdecomp_epoch_batched (one launch series when the models can share it,
+ * else one model after another); a model whose epoch completes moves to the
+ * next one (its epoch counter advances, the cursor returns to 0).  Windows of
+ * an epoch give the same result, bit for bit, as the whole epoch.  Jobs can
+ * thus join and leave a training batch every window instead of every epoch.
+ * While a model's cursor is not 0, stdecomp_epoch and stdecomp_epoch_batched
+ * refuse it (STD_E_STATE); stdecomp_set_epoch resets the cursor.  st: NULL or
+ * n records (minibatches and updates run; epochs_run = epochs completed).
+ * STD_E_INVAL for n < 1, a null array or max_minibatches < 1; otherwise as
+ * stdecomp_epoch_batched. */
+int stdecomp_step_batched(stdecomp_handle* const* hs, int32_t n, int64_t max_minibatches, stdecomp_epoch_stats* st);
+
 /* Measurement aid: the chain's grid barrier alone (the handle's W workgroups,
  * `reps` barriers in a row, 1 <= reps <= 1000000), timed with events on the
  * handle's stream; *us_per_barrier receives the mean time of one barrier in
@@ -253,7 +278,8 @@ int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out);
 /* Release the handle and its device memory (NULL is accepted). */
 int stdecomp_free(stdecomp_handle* h);
 
-/* Static message for a return code; the handle's last error message. */
+/* Static message for a return code; the handle's last error message (for
+ * h == NULL: why the calling thread's last stdecomp_init failed). */
 const char* stdecomp_strerror(int code);
 const char* stdecomp_last_error(const stdecomp_handle* h);
 

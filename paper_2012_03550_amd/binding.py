@@ -58,7 +58,7 @@ class LossOut(ctypes.Structure):
 class InfoOut(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int32), ("chunk", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("lds_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("minibatches", ctypes.c_int64), ("epoch", ctypes.c_int64)]
+                ("minibatches", ctypes.c_int64), ("epoch", ctypes.c_int64), ("cursor", ctypes.c_int64)]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -86,6 +86,8 @@ SIGNATURES = {
     "stdecomp_debug_barrier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "stdecomp_epoch_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
                                               ctypes.POINTER(EpochStats)]),
+    "stdecomp_step_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.POINTER(EpochStats)]),
     "stdecomp_free": (ctypes.c_int, [ctypes.c_void_p]),
     "stdecomp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stdecomp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -243,7 +245,7 @@ class Stdecomp:
         h = ctypes.c_void_p()
         rc = L.stdecomp_init(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h))
         if rc != STD_OK:
-            raise StdecompError(rc, "stdecomp_init failed (see stderr)")
+            raise StdecompError(rc, "stdecomp_init failed: %s" % L.stdecomp_last_error(None).decode())
         self._h = h
         self.nnz = nnz
         self.batch = batch
@@ -397,6 +399,18 @@ def epoch_batched(handles, n_epochs=1):
     rc = load().stdecomp_epoch_batched(arr, n, n_epochs, st)
     if rc != 0:
         handles[0]._check(rc, "stdecomp_epoch_batched")
+    return [{f: getattr(s, f) for f, _ in EpochStats._fields_} for s in st]
+
+
+def step_batched(handles, max_minibatches):
+    """Advance every model in ``handles`` by up to ``max_minibatches``
+    minibatches of its current epoch (continuous batching)."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h._h.value for h in handles])
+    st = (EpochStats * n)()
+    rc = load().stdecomp_step_batched(arr, n, max_minibatches, st)
+    if rc != 0:
+        handles[0]._check(rc, "stdecomp_step_batched")
     return [{f: getattr(s, f) for f, _ in EpochStats._fields_} for s in st]
 
 

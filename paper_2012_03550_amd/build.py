@@ -17,6 +17,11 @@ HIPCC_FLAGS = [
     "-std=c++17", "-O3", "--offload-arch=" + ARCH, "-fPIC",
     # packed FP32 instructions stay off (they are avoided on this hardware)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit fusion of a * b + c: whether the compiler fuses depends on
+    # the code around it (inlining, register pressure), and a chain must give
+    # the same bits alone and inside the batched kernel; fused operations are
+    # written as fmaf where they are wanted
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

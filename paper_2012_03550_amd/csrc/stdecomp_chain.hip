@@ -1190,6 +1190,7 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
   const ChainLayout& L = a.lay;
   const Shape& s = a.s;
   const int N = s.N, R = a.R, tid = threadIdx.x, BT = blockDim.x, chp = L.chp;
+  const int lane = tid & 63, wv = tid >> 6, nwaves = BT >> 6, r16 = lane & 15, kq = lane >> 4;
   float* Bs = lds + L.kb;
   float* wt = lds + L.kwt;
   float* g = lds + L.kg;  // full symmetric matrix, ke x ke (row stride ke)
@@ -1200,67 +1201,106 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
     const int E = R * Jn;
     const int ke = E + 1;
     const int lg = (ke * (ke + 1)) >> 1;
-    const int nb4 = (ke + 3) >> 2;
-    const int kpar = n & 1;  // partial buffers alternate between modes
-    // 1. rows of [W_0 .. W_{R-1} | x] for the chunk's samples (zero beyond the count)
+    const int T16 = (ke + 15) >> 4;  // 16-column tiles
+    const int kpar = n & 1;          // partial buffers alternate between modes
+    // 1. rows of [W_0 .. W_{R-1} | x] for the chunk's samples (zero beyond the
+    //    count and in the padding columns up to the tile edge)
     if (tid < chp) {
       float* wrow = wt + tid * L.kws;
       if (tid < cnt) {
         float an[JR];
         read_row<JR, BF, EXACT>(rowbuf, L.coff[n], chp, tid, Jn, an);
-        for (int c = 0; c < R; ++c) {
-          float q = 1.f;
+        for (int c0 = 0; c0 < R; c0 += 8) {  // eight columns at a time, the other modes' rows in registers
+          float q[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) q[u] = 1.f;
           for (int k = 0; k < N; ++k) {
             if (k == n) continue;
             const int Jk = EXACT ? JR : s.J[k];
-            const float* bk = Bs + L.kboff[k] + c;
-            float d = 0.f;
-            for (int j = 0; j < Jk; ++j) d = fmaf(row_at<BF>(rowbuf, L.coff[k], chp, tid, j), bk[j * R], d);
-            q *= d;
+            float rk[JR];
+            read_row<JR, BF, EXACT>(rowbuf, L.coff[k], chp, tid, Jk, rk);
+            const float* bk = Bs + L.kboff[k] + c0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (c0 + u < R) {
+                float d = 0.f;
+#pragma unroll
+                for (int j = 0; j < JR; ++j)
+                  if (EXACT || j < Jk) d = fmaf(rk[j], bk[j * R + u], d);
+                q[u] *= d;
+              }
+            }
           }
 #pragma unroll
-          for (int aa = 0; aa < JR; ++aa)
-            if (EXACT || aa < Jn) wrow[c * Jn + aa] = an[aa] * q;
+          for (int u = 0; u < 8; ++u) {
+            if (c0 + u < R) {
+#pragma unroll
+              for (int aa = 0; aa < JR; ++aa)
+                if (EXACT || aa < Jn) wrow[(c0 + u) * Jn + aa] = an[aa] * q[u];
+            }
+          }
         }
         wrow[E] = x;
       } else {
         for (int e = 0; e < ke; ++e) wrow[e] = 0.f;
       }
-      for (int e = ke; e < 4 * nb4; ++e) wrow[e] = 0.f;
+      for (int e = ke; e < 16 * T16; ++e) wrow[e] = 0.f;
     }
     __syncthreads();
-    // 2. this chunk's Gram matrix, packed upper triangle, in 4 x 4 blocks
-    float* part = a.partial + ((size_t)kpar * a.W + w) * klgp;
-    const int npairs = (nb4 * (nb4 + 1)) >> 1;
-    for (int pi = tid; pi < npairs; pi += BT) {
-      int bi = 0, rem = pi;
-      while (rem >= nb4 - bi) {
-        rem -= nb4 - bi;
-        ++bi;
-      }
-      const int bj = bi + rem;
-      f32x4 acc[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-      for (int p = 0; p < chp; ++p) {
-        const f32x4 u = *reinterpret_cast<const f32x4*>(wt + p * L.kws + 4 * bi);
-        const f32x4 v = *reinterpret_cast<const f32x4*>(wt + p * L.kws + 4 * bj);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] += u[i] * v;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int e1 = 4 * bi + i, e2 = 4 * bj + jj;
-          if (e1 <= e2 && e2 < ke) part[tri_index(e1, e2, ke)] = acc[i][jj];
+    // 2. this chunk's Gram matrix [W|x]^T [W|x] (MFMA 16x16x4, K = samples):
+    //    the upper-triangle tile pairs, one per wave at a time, the operands of
+    //    the next four K steps read before the MFMAs of these; only entries
+    //    e1 <= e2 < ke are stored (packed upper triangle)
+    {
+      float* part = a.partial + ((size_t)kpar * a.W + w) * klgp;
+      const int npairs = (T16 * (T16 + 1)) >> 1;
+      const int ngroups = chp >> 4;  // four K steps (16 samples) per group; chp is a multiple of 32
+      for (int pi = wv; pi < npairs; pi += nwaves) {
+        int ti = 0, rem = pi;
+        while (rem >= T16 - ti) {
+          rem -= T16 - ti;
+          ++ti;
         }
+        const int tj = ti + rem;
+        const float* colA = wt + 16 * ti + r16;
+        const float* colB = wt + 16 * tj + r16;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        float av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = colA[(4 * u + kq) * L.kws];
+          bv[u] = colB[(4 * u + kq) * L.kws];
+        }
+        for (int gi = 0; gi < ngroups; ++gi) {
+          const int gn = gi + 1 < ngroups ? gi + 1 : gi;
+          float an2[4], bn2[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            an2[u] = colA[(16 * gn + 4 * u + kq) * L.kws];
+            bn2[u] = colB[(16 * gn + 4 * u + kq) * L.kws];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[u] = an2[u];
+            bv[u] = bn2[u];
+          }
+        }
+        const int e2 = 16 * tj + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e1 = 16 * ti + 4 * kq + i;
+          if (e1 <= e2 && e2 < ke) part[tri_index(e1, e2, ke)] = acc[i];
+        }
+      }
     }
     passed += 1;
     barrier_arrive(a, w, passed);
     if (!barrier_wait(a, passed, flag_lds)) return false;
     // 3. this workgroup's slice of the sum over workgroups (groups of threads
-    //    add runs of workgroups in order, then the groups are added in order)
+    //    add runs of workgroups in order, eight loads in flight, then the
+    //    groups are added in order)
     {
       const float* pb = a.partial + (size_t)kpar * a.W * klgp;
       float* gs = a.partial + (size_t)2 * a.W * klgp + (size_t)kpar * klgp;
@@ -1271,8 +1311,16 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
         const int i = tid % per, grp = tid / per;
         if (grp < ng) {
           float sum = 0.f;
-          if (e0 + i < e1)
-            for (int v = grp * vg; v < min(a.W, (grp + 1) * vg); ++v) sum += pb[(size_t)v * klgp + e0 + i];
+          const int e = min(e0 + i, lg - 1);
+          const int v1 = min(a.W, (grp + 1) * vg);
+          for (int v = grp * vg; v < v1; v += 8) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = pb[(size_t)min(v + u, a.W - 1) * klgp + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (v + u < v1) sum += t[u];
+          }
           g[grp * per + i] = sum;
         }
         __syncthreads();
@@ -1284,7 +1332,14 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
       } else {
         for (int e = e0 + tid; e < e1; e += BT) {
           float sum = 0.f;
-          for (int v = 0; v < a.W; ++v) sum += pb[(size_t)v * klgp + e];
+          for (int v = 0; v < a.W; v += 8) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = pb[(size_t)min(v + u, a.W - 1) * klgp + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (v + u < a.W) sum += t[u];
+          }
           gs[e] = sum;
         }
       }
@@ -1292,17 +1347,27 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
     passed += 1;
     barrier_arrive(a, w, passed);
     if (!barrier_wait(a, passed, flag_lds)) return false;
-    // 4. the summed matrix, unpacked (every workgroup)
+    // 4. the summed matrix (every workgroup): the packed triangle into the
+    //    [W | x] region, which the Gram is done with (coalesced, eight loads in
+    //    flight), then unpacked within LDS
     {
       const float* gs = a.partial + (size_t)2 * a.W * klgp + (size_t)kpar * klgp;
-      for (int e = tid; e < ke * ke; e += BT) {
-        const int r1 = e / ke, c1 = e - r1 * ke;
-        g[e] = gs[r1 <= c1 ? tri_index(r1, c1, ke) : tri_index(c1, r1, ke)];
+      for (int e0 = tid; e0 < lg; e0 += 8 * BT) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = gs[min(e0 + u * BT, lg - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e0 + u * BT < lg) wt[e0 + u * BT] = t[u];
       }
+      __syncthreads();
+      for (int r1 = wv; r1 < ke; r1 += nwaves)
+        for (int c1 = lane; c1 < ke; c1 += 64)
+          g[r1 * ke + c1] = wt[r1 <= c1 ? tri_index(r1, c1, ke) : tri_index(c1, r1, ke)];
     }
     __syncthreads();
     // 5. the column steps, c = 0 .. R-1 in order: row a of V_c by a group of
-    //    TPR lanes (a power of two within one wave), summed by xor shuffles
+    //    tpr lanes (a power of two within one wave), summed by xor shuffles
     {
       float* Bn = Bs + L.kboff[n];
       int tpr = 64;
@@ -1336,13 +1401,15 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
   // 6. the core of the updated B: G[lin] = sum_r prod_k B(k)[j_k, r]
   float* Gs = lds + L.gs;
   for (int lin = tid; lin < s.P; lin += BT) {
+    int jo[kMaxOrder];
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k) jo[k] = k < N ? L.kboff[k] + ((lin / s.lstride[k]) % s.J[k]) * R : 0;
     float acc = 0.f;
     for (int r = 0; r < R; ++r) {
       float t = 1.f;
-      for (int k = 0; k < N; ++k) {
-        const int jk = (lin / s.lstride[k]) % s.J[k];
-        t *= Bs[L.kboff[k] + jk * R + r];
-      }
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k)
+        if (k < N) t *= Bs[jo[k] + r];
       acc += t;
     }
     Gs[lin] = acc;
@@ -1440,7 +1507,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
     }
   }
 
-  unsigned passed = 0;
+  unsigned passed = a.passed0;
   int ppar = 0;  // carry parity written by the previous phase
   int par = 0;   // carry parity of the current phase
   bool first = true;
@@ -1849,15 +1916,25 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
   chain_body<JU, NU, BFI>(a, blockIdx.x);
 }
 
-// Several independent chains in one cooperative launch (one per tensor of a
-// batch): workgroup g runs workgroup map[g].y of chain map[g].x, whose
-// arguments (own buffers, barrier flags and minibatch range) are all[map[g].x].
-// A chain with an empty range exits at once; the others never wait for it.
-template <int JU, int NU, int BFI>
-__global__ __launch_bounds__(kChainThreads) void k_chain_multi(const ChainArgs* __restrict__ all,
-                                                               const int2* __restrict__ map) {
-  const int2 m = map[blockIdx.x];
-  chain_body<JU, NU, BFI>(all[m.x], m.y);
+// Many independent chains in one cooperative launch (a batch of tensors):
+// slot q = the workgroups [q W, (q + 1) W) runs its list of chains one after
+// another, workgroup w of the slot as workgroup w of each chain.  The slot's
+// barrier flags keep counting from one chain to the next (each chain's
+// passed0 says where it starts), so nothing is reset between chains.  The
+// lists are balanced on the host (longest first, to the least loaded slot).
+template <int NU, int BFI>
+__global__ __launch_bounds__(kChainThreads) void k_chain_queue(const ChainArgs* __restrict__ all,
+                                                               const int* __restrict__ list, int nslots, int W) {
+  const int q = blockIdx.x / W, w = blockIdx.x - q * W;
+  const int* models = list + nslots + 1;
+  for (int i = list[q]; i < list[q + 1]; ++i) {
+    const ChainArgs& a = all[models[i]];
+    // (the body a chain runs alone, so that results are bit-identical)
+    STDK_FOR_VARIANT(a.jv, (chain_body<JU, NU, BFI>(a, w)));
+    // a workgroup of this chain gave up waiting: the slot's flags no longer
+    // count in step, so the slot stops (the host reports the error)
+    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  }
 }
 
 // The chain's grid barrier alone, `reps` times in a row (no other work): the
@@ -1977,9 +2054,10 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
       o += s.J[k] * a.R;
     }
     L.ke = a.R * jmax + 1;
-    L.kws = pad4(L.ke);
+    L.kws = ((L.ke + 15) & ~15) + 1;  // whole 16-column tiles, odd stride
     L.klg = (L.ke * (L.ke + 1)) / 2;
-    const size_t need = al((size_t)L.chp * L.kws) + al(std::max((size_t)L.ke * L.ke, (size_t)threads));
+    const size_t need = al(std::max((size_t)L.chp * L.kws, (size_t)L.klg)) +
+                        al(std::max((size_t)L.ke * L.ke, (size_t)threads));
     const size_t have = al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) + al((size_t)L.chp * L.ras);
     kr_extra = need > have ? need - have : 0;
   }
@@ -2002,7 +2080,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras) + kr_extra;
   L.kwt = L.hp;
-  L.kg = L.hp + (int)al((size_t)L.chp * L.kws);
+  L.kg = L.hp + (int)al(std::max((size_t)L.chp * L.kws, (size_t)L.klg));
   L.kb = (int)off;    off += kb_len;
   L.split = (int)off; off += al((size_t)a.split_cap * L.sstride);
   L.cbuf = (int)off;  off += al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0);
@@ -2128,42 +2206,33 @@ hipError_t launch_chain_n(const ChainArgs& a, int threads, size_t bytes, hipStre
   return n3 ? launch_chain_t<JU, 3, 0>(a, threads, bytes, st) : launch_chain_t<JU, 0, 0>(a, threads, bytes, st);
 }
 
-template <int JU, int NU, int BFI>
-hipError_t launch_multi_t(const ChainArgs* dev_args, const int* dev_map, int wgs, int threads, size_t bytes,
+template <int JU>
+hipError_t launch_kruskal_n(const ChainArgs& a, int threads, size_t bytes, hipStream_t st, int f) {
+  const bool n3 = a.s.N == 3;
+  if (f == 3) return n3 ? launch_chain_t<JU, 3, 3>(a, threads, bytes, st) : launch_chain_t<JU, 0, 3>(a, threads, bytes, st);
+  return n3 ? launch_chain_t<JU, 3, 2>(a, threads, bytes, st) : launch_chain_t<JU, 0, 2>(a, threads, bytes, st);
+}
+
+template <int NU, int BFI>
+hipError_t launch_queue_t(const ChainArgs* dev_args, const int* dev_list, int nslots, int W, int threads, size_t bytes,
                           hipStream_t st) {
   const ChainArgs* pa = dev_args;
-  const int2* pm = reinterpret_cast<const int2*>(dev_map);
-  void* params[] = {&pa, &pm};
-  hipError_t e = hipFuncSetAttribute((const void*)k_chain_multi<JU, NU, BFI>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const int* pl = dev_list;
+  void* params[] = {&pa, &pl, &nslots, &W};
+  hipError_t e = hipFuncSetAttribute((const void*)k_chain_queue<NU, BFI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
   if (e == hipSuccess)
-    e = hipLaunchCooperativeKernel((const void*)k_chain_multi<JU, NU, BFI>, dim3(wgs), dim3(threads), params,
+    e = hipLaunchCooperativeKernel((const void*)k_chain_queue<NU, BFI>, dim3(nslots * W), dim3(threads), params,
                                    (unsigned)bytes, st);
   return e;
 }
 
-template <int JU>
-hipError_t launch_multi_j(int n3, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs, int threads,
-                          size_t bytes, hipStream_t st) {
-  if (bf) return n3 ? launch_multi_t<JU, 3, 1>(dev_args, dev_map, wgs, threads, bytes, st)
-                    : launch_multi_t<JU, 0, 1>(dev_args, dev_map, wgs, threads, bytes, st);
-  return n3 ? launch_multi_t<JU, 3, 0>(dev_args, dev_map, wgs, threads, bytes, st)
-            : launch_multi_t<JU, 0, 0>(dev_args, dev_map, wgs, threads, bytes, st);
-}
-
-bool chain_multi_supported(const Shape& s) {
-  const int v = chain_variant(s);
-  return v == 4 || v == 8 || v == 16;
-}
-
-hipError_t launch_chain_multi(const Shape& s, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs,
+hipError_t launch_chain_queue(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
                               int threads, size_t bytes, hipStream_t st) {
-  const int v = chain_variant(s);
-  const int n3 = s.N == 3;
-  if (v == 4) return launch_multi_j<4>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
-  if (v == 8) return launch_multi_j<8>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
-  if (v == 16) return launch_multi_j<16>(n3, bf, dev_args, dev_map, wgs, threads, bytes, st);
-  return hipErrorInvalidValue;
+  if (bf) return n3 ? launch_queue_t<3, 1>(dev_args, dev_list, nslots, W, threads, bytes, st)
+                    : launch_queue_t<0, 1>(dev_args, dev_list, nslots, W, threads, bytes, st);
+  return n3 ? launch_queue_t<3, 0>(dev_args, dev_list, nslots, W, threads, bytes, st)
+            : launch_queue_t<0, 0>(dev_args, dev_list, nslots, W, threads, bytes, st);
 }
 
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
@@ -2176,10 +2245,14 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
         chk.lay.hm_len != a.lay.hm_len || !a.aux)
       return hipErrorInvalidValue;
   }
-  if (a.R > 0) {  // Kruskal core: the generic-rank kernels
-    const bool n3 = a.s.N == 3;
-    if (a.bf16) return n3 ? launch_chain_t<0, 3, 3>(a, threads, bytes, st) : launch_chain_t<0, 0, 3>(a, threads, bytes, st);
-    return n3 ? launch_chain_t<0, 3, 2>(a, threads, bytes, st) : launch_chain_t<0, 0, 2>(a, threads, bytes, st);
+  if (a.R > 0) {  // Kruskal core: kernels for equal ranks 5, 8, 10, else the generic-rank ones
+    const int f = a.bf16 ? 3 : 2;
+    switch (var) {
+      case 5: return launch_kruskal_n<5>(a, threads, bytes, st, f);
+      case 8: return launch_kruskal_n<8>(a, threads, bytes, st, f);
+      case 10: return launch_kruskal_n<10>(a, threads, bytes, st, f);
+      default: return launch_kruskal_n<0>(a, threads, bytes, st, f);
+    }
   }
   hipError_t e = hipSuccess;
   if (a.bf16) {

@@ -140,6 +140,8 @@ struct ChainArgs {
   int chunk;                // samples per workgroup per phase (<= blockDim)
   int carry_stride;         // floats per carry slot
   long long spin_limit;     // barrier give-up bound (iterations)
+  unsigned passed0;         // barriers the flags in bar have counted before this chain starts
+  int jv;                   // rank variant of the chain body (chain_variant of s)
   int split_cap;            // entries of the LDS split-row table
   ChainLayout lay;          // filled by plan_chain_lds
   PhaseTab pt[kMaxOrder + 1];
@@ -164,12 +166,15 @@ hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const
 size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st);
-// Several chains of one kernel variant (equal rank 4, 8 or 16; the same order
-// class and dtype) in one cooperative launch: dev_args[t] are chain t's
-// arguments, dev_map[2 g], dev_map[2 g + 1] = (chain, workgroup) of grid
-// workgroup g; bytes = the largest LDS plan among them.
-bool chain_multi_supported(const Shape& s);
-hipError_t launch_chain_multi(const Shape& s, int bf, const ChainArgs* dev_args, const int* dev_map, int wgs,
+// Many independent chains in one cooperative launch: slot q (workgroups
+// [q W, (q + 1) W)) runs the chains list[nslots + 1 + i], i in [list[q],
+// list[q + 1]), one after another, each from its own arguments dev_args[m]
+// (own buffers and minibatch range; bar = the slot's flags, passed0 = the
+// barriers the slot counted before it).  Every chain has W workgroups, the
+// same order class (three modes or other), the dense core and the same
+// dtype; ranks may differ (each chain runs the body it runs alone).  bytes = the
+// largest LDS plan among them.
+hipError_t launch_chain_queue(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
                               int threads, size_t bytes, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
                                uint32_t* rec, int* bad, hipStream_t st);

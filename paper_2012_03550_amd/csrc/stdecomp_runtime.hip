@@ -3,6 +3,7 @@
 // in include/stdecomp.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,8 +25,10 @@ struct stdecomp_handle {
   uint64_t seed_sample = 0;
   int dtype = 0;
   int64_t epoch = 0;
+  int64_t cursor = 0;  // next minibatch of epoch `epoch` for stdecomp_step_batched (0: at an epoch start)
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t qstream = nullptr;  // predictions (may run while another thread trains the handle)
   int device = 0;
   int num_cus = 0;
   // chain configuration
@@ -58,9 +61,11 @@ struct stdecomp_handle {
   double* dscratch = nullptr;  // loss/sum-of-squares block partials
   int dscratch_blocks = 0;
   int* flag = nullptr;
+  int* qflag = nullptr;  // bad-index flag of the prediction calls
   size_t device_bytes = 0;
   int64_t sched_epoch = -1;  // epoch whose schedule coo_perm/sigma hold
   std::string last_error;
+  std::mutex err_mu;  // last_error may be set by a prediction beside a training call
   hipEvent_t ev[4] = {};
   stdecomp_alloc_fn dev_alloc = nullptr;  // caller's device allocator (NULL: hipMalloc)
   stdecomp_free_fn dev_free = nullptr;
@@ -79,7 +84,10 @@ static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 namespace {
 
 int fail(stdecomp_handle* h, int code, const std::string& msg) {
-  if (h) h->last_error = msg;
+  if (h) {
+    std::lock_guard<std::mutex> lock(h->err_mu);
+    h->last_error = msg;
+  }
   return code;
 }
 
@@ -105,6 +113,9 @@ struct BatchWorkspace {
   Dev dev[64];
 };
 BatchWorkspace g_batch_ws;
+
+// Why the calling thread's last stdecomp_init failed (stdecomp_last_error(NULL)).
+thread_local std::string g_init_error;
 
 // Per-device address of the scratch array (filled by resolve_scratch).
 struct ScratchTable {
@@ -147,13 +158,16 @@ constexpr long long kSpinLimit = 1ll << 24;
 
 // Device memory of a handle: from the caller's allocator when the options
 // give one (stdecomp_options.dev_alloc / dev_free), else hipMalloc / hipFree.
+// account: count the buffer in device_bytes (buffers held by the handle; the
+// temporary buffers of a call are not counted).  st: the stream the buffer is
+// used on (the handle's stream by default).
 template <typename T>
-int dalloc(stdecomp_handle* h, T** p, size_t count) {
+int dalloc(stdecomp_handle* h, T** p, size_t count, bool account = true, hipStream_t st = nullptr) {
   *p = nullptr;
   if (count == 0) count = 1;
   const size_t bytes = count * sizeof(T);
   if (h->dev_alloc) {
-    void* q = h->dev_alloc(h->alloc_ctx, bytes, (void*)h->stream);
+    void* q = h->dev_alloc(h->alloc_ctx, bytes, (void*)(st ? st : h->stream));
     if (!q) return fail(h, STD_E_NOMEM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
     *p = static_cast<T*>(q);
   } else {
@@ -164,14 +178,14 @@ int dalloc(stdecomp_handle* h, T** p, size_t count) {
       return fail(h, STD_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     }
   }
-  h->device_bytes += bytes;
+  if (account) h->device_bytes += bytes;
   return STD_OK;
 }
 
 template <typename T>
-void dfree(stdecomp_handle* h, T*& p) {
+void dfree(stdecomp_handle* h, T*& p, hipStream_t st = nullptr) {
   if (p) {
-    if (h->dev_free) h->dev_free(h->alloc_ctx, (void*)p, (void*)h->stream);
+    if (h->dev_free) h->dev_free(h->alloc_ctx, (void*)p, (void*)(st ? st : h->stream));
     else (void)hipFree((void*)p);
   }
   p = nullptr;
@@ -311,10 +325,11 @@ int run_schedule(stdecomp_handle* h, int64_t epoch) {
   return STD_OK;
 }
 
-// Pack caller COO (host or device SoA) into device records.  *rec_out is
-// freshly allocated (caller frees).  Index range violations -> STD_E_INVAL.
+// Pack caller COO (host or device SoA) into device records on stream st
+// (bad-index flag `flag`).  *rec_out is freshly allocated (caller frees it on
+// st).  Index range violations -> STD_E_INVAL.
 int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const float* vals, int on_device,
-                        uint32_t** rec_out) {
+                        uint32_t** rec_out, hipStream_t st, int* flag) {
   *rec_out = nullptr;
   const int N = h->s.N;
   const int32_t* didx = idx;
@@ -327,43 +342,40 @@ int pack_caller_entries(stdecomp_handle* h, int64_t n, const int32_t* idx, const
         const int32_t v = idx[(int64_t)k * n + t];
         if (v < 0 || v >= h->s.I[k]) return fail(h, STD_E_INVAL, "index out of range");
       }
-    int rc = dalloc(h, &tidx, (size_t)N * n);
+    int rc = dalloc(h, &tidx, (size_t)N * n, false, st);
     if (rc) return rc;
-    h->device_bytes -= (size_t)N * n * 4;
-    HIPCHK(h, hipMemcpyAsync(tidx, idx, (size_t)N * n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(tidx, idx, (size_t)N * n * 4, hipMemcpyHostToDevice, st));
     if (vals) {
-      rc = dalloc(h, &tvals, (size_t)n);
+      rc = dalloc(h, &tvals, (size_t)n, false, st);
       if (rc) {
-        dfree(h, tidx);
+        dfree(h, tidx, st);
         return rc;
       }
-      h->device_bytes -= (size_t)n * 4;
-      HIPCHK(h, hipMemcpyAsync(tvals, vals, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(tvals, vals, (size_t)n * 4, hipMemcpyHostToDevice, st));
     }
     didx = tidx;
     dvals = tvals;
   }
   uint32_t* rec = nullptr;
-  int rc = dalloc(h, &rec, (size_t)n * h->s.R);
+  int rc = dalloc(h, &rec, (size_t)n * h->s.R, false, st);
   if (rc) {
-    dfree(h, tidx);
-    dfree(h, tvals);
+    dfree(h, tidx, st);
+    dfree(h, tvals, st);
     return rc;
   }
-  h->device_bytes -= (size_t)n * h->s.R * 4;
-  HIPCHK(h, hipMemsetAsync(h->flag, 0, sizeof(int), h->stream));
-  hipError_t e = stdk::launch_pack_records(h->s, didx, dvals, n, rec, h->flag, h->stream);
+  hipError_t e = stdk::launch_fill_i32(flag, 0, 1, st);
+  if (e == hipSuccess) e = stdk::launch_pack_records(h->s, didx, dvals, n, rec, flag, st);
   int bad = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(h, tidx);
-  dfree(h, tvals);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(h, tidx, st);
+  dfree(h, tvals, st);
   if (e != hipSuccess) {
-    dfree(h, rec);
+    dfree(h, rec, st);
     return hip_fail(h, e, "packing entries");
   }
   if (bad) {
-    dfree(h, rec);
+    dfree(h, rec, st);
     return fail(h, STD_E_INVAL, "index out of range");
   }
   *rec_out = rec;
@@ -458,9 +470,11 @@ void release(stdecomp_handle* h) {
   dfree(h, h->nf);
   dfree(h, h->dscratch);
   dfree(h, h->flag);
+  dfree(h, h->qflag);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->qstream) (void)hipStreamDestroy(h->qstream);
 }
 
 bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.f; }
@@ -492,7 +506,10 @@ const char* stdecomp_strerror(int code) {
   }
 }
 
-const char* stdecomp_last_error(const stdecomp_handle* h) { return h ? h->last_error.c_str() : "no handle"; }
+const char* stdecomp_last_error(const stdecomp_handle* h) {
+  if (h) return h->last_error.c_str();
+  return g_init_error.empty() ? "no handle" : g_init_error.c_str();
+}
 
 int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp_handle** out) {
   if (!out) return STD_E_INVAL;
@@ -528,6 +545,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   h->train_rmse = o->report_train_rmse != 0;
   auto bail = [&](int rc) {
     std::fprintf(stderr, "stdecomp_init: %s\n", h->last_error.c_str());
+    g_init_error = h->last_error;
     release(h);
     delete h;
     return rc;
@@ -585,6 +603,11 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     }
     h->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&h->qstream, hipStreamNonBlocking) != hipSuccess) {
+    h->qstream = nullptr;
+    h->last_error = "hipStreamCreate failed";
+    return bail(STD_E_DEVICE);
+  }
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       h->last_error = "hipEventCreate failed";
@@ -605,7 +628,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||
       (rc = dalloc(h, &h->bar, (size_t)h->W * stdk::kFlagStride)) ||
       (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->nf, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) ||
-      (rc = dalloc(h, &h->flag, 1)))
+      (rc = dalloc(h, &h->flag, 1)) || (rc = dalloc(h, &h->qflag, 1)))
     return bail(rc);
   for (int n = 0; n < N; ++n) {
     h->Jb[n] = (s.J[n] + 7) & ~7;
@@ -718,6 +741,23 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
 
 namespace {
 
+// Algorithmic flops per nonzero-update.  Dense core: (2N + 4) prod(J) (the
+// core step's contraction and gradient, and each mode's contraction).  Kruskal
+// core: each mode's contraction, 2N prod(J), plus per mode n the row of
+// [W | x] (R sum_{k != n} J_k dot-product terms and R J_n products) and its
+// packed Gram matrix ((R J_n + 1)(R J_n + 2) / 2 multiply-adds).
+double flops_per_update(const stdecomp_handle* h) {
+  const stdk::Shape& s = h->s;
+  if (h->R <= 0) return (2.0 * s.N + 4.0) * s.P;
+  double f = 2.0 * s.N * s.P, sumJ = 0.0;
+  for (int n = 0; n < s.N; ++n) sumJ += s.J[n];
+  for (int n = 0; n < s.N; ++n) {
+    const double e = (double)h->R * s.J[n] + 1.0;
+    f += 2.0 * h->R * (sumJ - s.J[n]) + (double)h->R * s.J[n] + e * (e + 1.0);
+  }
+  return f;
+}
+
 // STD_E_DIVERGED naming the first non-finite parameter the chain wrote
 // (stdk::nf_key of the record; all ones means none was recorded).
 int diverged_at(stdecomp_handle* h, int64_t epoch, unsigned long long key) {
@@ -729,6 +769,30 @@ int diverged_at(stdecomp_handle* h, int64_t epoch, unsigned long long key) {
                               : "mode-" + std::to_string(ph - 1) + " sub-step, row " + std::to_string(row);
   return fail(h, STD_E_DIVERGED, "non-finite parameters: first at epoch " + std::to_string(epoch) + ", minibatch " +
                                      std::to_string(b) + (b == (1ll << 29) - 1 ? " or later" : "") + ", " + where);
+}
+
+// Work of minibatches [b0, b1) into *acc: minibatches, nonzero-updates,
+// algorithmic bytes (COO records; each touched row read and written once per
+// minibatch and mode, 8 bytes per value in FP32, 12 in BF16 with its FP32
+// master; the core, or the Kruskal factors, read and written once per
+// minibatch) and algorithmic flops.  nseg_host: the distinct rows of every
+// (minibatch, mode) of the epoch, as counted by the row-set sort.
+void add_work(const stdecomp_handle* h, int64_t b0, int64_t b1, const std::vector<int>& nseg_host,
+              stdecomp_epoch_stats* acc) {
+  const int N = h->s.N;
+  const double beta = h->dtype == STD_DTYPE_BF16 ? 12.0 : 8.0;
+  double rows_bytes = 0.0;
+  int64_t upd = 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t m = (h->T - b * h->M < h->M) ? h->T - b * h->M : h->M;
+    upd += m;
+    for (int n = 0; n < N; ++n) rows_bytes += (double)nseg_host[(size_t)b * N + n] * h->s.J[n] * beta;
+  }
+  acc->minibatches += b1 - b0;
+  acc->updates += upd;
+  const double core_words = h->R > 0 ? (double)h->nB : (double)h->s.P;
+  acc->bytes_alg += (double)upd * (4.0 * N + 4.0) + rows_bytes + (double)(b1 - b0) * 2.0 * core_words * 4.0;
+  acc->flops_alg += (double)upd * flops_per_update(h);
 }
 
 // Minibatches [b0, b1) of epoch `epoch`, accumulated into *acc.
@@ -767,19 +831,7 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
   acc->schedule_seconds += t01 * 1e-3;
   acc->chain_seconds += t12 * 1e-3;
   acc->device_seconds += (t01 + t12) * 1e-3;
-  acc->minibatches += b1 - b0;
-  // algorithmic bytes: COO records, each touched row read and written once
-  // per minibatch and mode, the core read and written once per minibatch
-  double rows_bytes = 0.0;
-  int64_t upd = 0;
-  for (int64_t b = b0; b < b1; ++b) {
-    const int64_t m = (h->T - b * h->M < h->M) ? h->T - b * h->M : h->M;
-    upd += m;
-    for (int n = 0; n < N; ++n) rows_bytes += (double)nseg_host[(size_t)b * N + n] * h->s.J[n] * 8.0;
-  }
-  acc->updates += upd;
-  acc->bytes_alg += (double)upd * (4.0 * N + 4.0) + rows_bytes + (double)(b1 - b0) * 2.0 * h->s.P * 4.0;
-  acc->flops_alg += (double)upd * (2.0 * N + 4.0) * h->s.P;
+  add_work(h, b0, b1, nseg_host, acc);
   return STD_OK;
 }
 
@@ -802,6 +854,7 @@ extern "C" {
 int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* st) {
   if (!h) return STD_E_STATE;
   if (n_epochs < 0) return fail(h, STD_E_INVAL, "n_epochs < 0");
+  if (h->cursor != 0) return fail(h, STD_E_STATE, "the model is inside an epoch (stdecomp_step_batched)");
   stdecomp_epoch_stats acc{};
   acc.train_rmse = std::nan("");
   std::vector<int> nseg_host;
@@ -821,49 +874,78 @@ int stdecomp_epoch(stdecomp_handle* h, int32_t n_epochs, stdecomp_epoch_stats* s
   return rc;
 }
 
-int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st) {
-  if (!hs || n < 1) return STD_E_INVAL;
-  for (int i = 0; i < n; ++i)
-    if (!hs[i]) return STD_E_STATE;
-  stdecomp_handle* h0 = hs[0];
-  if (n_epochs < 0) return fail(h0, STD_E_INVAL, "n_epochs < 0");
-  // one launch needs the same kernel variant, device and dtype, distinct
-  // handles, and room for every chain's workgroups at once
-  bool one_launch = stdk::chain_multi_supported(h0->s) && h0->R == 0;
-  int total_w = 0;
-  size_t lds = 0;
-  for (int i = 0; i < n && one_launch; ++i) {
+}  // extern "C"
+
+namespace {
+
+// Whether the handles can share one batched launch: distinct handles on one
+// device with the same dtype, workgroup count, threads and order class
+// (three modes or other), all with the dense core; ranks may differ.
+bool batch_compatible(stdecomp_handle* const* hs, int n, size_t* lds) {
+  const stdecomp_handle* h0 = hs[0];
+  bool ok = h0->R == 0 && h0->W <= h0->num_cus;
+  *lds = 0;
+  for (int i = 0; i < n && ok; ++i) {
     const stdecomp_handle* h = hs[i];
-    one_launch = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads && h->R == 0 &&
-                 stdk::chain_variant(h->s) == stdk::chain_variant(h0->s) && (h->s.N == 3) == (h0->s.N == 3);
-    for (int k = 0; k < i && one_launch; ++k) one_launch = hs[k] != h;
-    total_w += h->W;
-    lds = h->chain_lds > lds ? h->chain_lds : lds;
+    ok = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads && h->R == 0 &&
+         h->W == h0->W && (h->s.N == 3) == (h0->s.N == 3);
+    for (int k = 0; k < i && ok; ++k) ok = hs[k] != h;
+    *lds = h->chain_lds > *lds ? h->chain_lds : *lds;
   }
-  if (one_launch && total_w > h0->num_cus) one_launch = false;
-  if (!one_launch) {  // the same updates, one handle after another
-    for (int i = 0; i < n; ++i) {
-      int rc = stdecomp_epoch(hs[i], n_epochs, st ? &st[i] : nullptr);
-      if (rc) return rc;
-    }
-    return STD_OK;
-  }
+  return ok;
+}
+
+// Minibatches [b0[i], b1[i]) of each handle's current epoch, every chain in
+// one cooperative launch per window of kBatchesPerLaunch minibatches: slots of
+// W workgroups, as many as the device holds at once and the batch needs; the
+// chains go to slots longest first, each to the slot with the least work so
+// far (work ~ minibatches x sub-steps x (1 + prod(J) / 512), a cost model of
+// the chain's latency-bound minibatch), and a slot runs its chains one after
+// another.  acc[i] receives the work and the launches' time (the whole
+// batched launch for every model).  Errors are reported on hs[0].
+int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std::vector<int64_t>& b0,
+                       const std::vector<int64_t>& b1, std::vector<stdecomp_epoch_stats>& acc) {
+  stdecomp_handle* h0 = hs[0];
+  const int W = h0->W;
   if (hipSetDevice(h0->device) != hipSuccess) return fail(h0, STD_E_DEVICE, "hipSetDevice failed");
-  std::vector<int> map((size_t)2 * total_w);
-  int64_t max_nb = 0;
-  for (int i = 0, g = 0; i < n; ++i) {
-    for (int w = 0; w < hs[i]->W; ++w, ++g) {
-      map[2 * g] = i;
-      map[2 * g + 1] = w;
-    }
-    max_nb = hs[i]->nb > max_nb ? hs[i]->nb : max_nb;
+  const int nslots = std::min(n, h0->num_cus / W);
+  std::vector<int> order((size_t)n);
+  std::vector<double> cost((size_t)n);
+  int64_t max_len = 0;
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    cost[i] = (double)(b1[i] - b0[i]) * (hs[i]->s.N + 1) * (1.0 + hs[i]->s.P / 512.0);
+    max_len = std::max(max_len, b1[i] - b0[i]);
   }
-  // the launch's argument table and workgroup map live in a per-device
-  // workspace that grows on demand and is kept, so a call allocates only when
-  // it needs more than any call before it on that device
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<std::vector<int>> slot_models((size_t)nslots);
+  std::vector<double> load((size_t)nslots, 0.0);
+  for (int i : order) {
+    int q = 0;
+    for (int k = 1; k < nslots; ++k)
+      if (load[k] < load[q]) q = k;
+    slot_models[q].push_back(i);
+    load[q] += cost[i];
+  }
+  std::vector<int> list((size_t)nslots + 1 + n);
+  {
+    int o = 0;
+    for (int q = 0; q < nslots; ++q) {
+      list[q] = o;
+      for (int i : slot_models[q]) list[(size_t)nslots + 1 + o++] = i;
+    }
+    list[nslots] = o;
+  }
+  // the launch's argument table, slot lists and barrier flags live in a
+  // per-device workspace that grows on demand and is kept, so a call
+  // allocates only when it needs more than any call before it on that device
   std::lock_guard<std::mutex> lock(g_batch_ws.mu);
   BatchWorkspace::Dev& ws = g_batch_ws.dev[h0->device];
-  const size_t need = ((sizeof(stdk::ChainArgs) * n + 255) & ~(size_t)255) + sizeof(int) * map.size();
+  auto pad256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t args_bytes = pad256(sizeof(stdk::ChainArgs) * n);
+  const size_t list_bytes = pad256(sizeof(int) * list.size());
+  const size_t flag_bytes = (size_t)nslots * W * stdk::kFlagStride * sizeof(unsigned);
+  const size_t need = args_bytes + list_bytes + flag_bytes;
   if (ws.bytes < need) {
     if (ws.ptr) (void)hipFree(ws.ptr);
     ws.ptr = nullptr;
@@ -876,69 +958,157 @@ int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epoc
     ws.bytes = need;
   }
   stdk::ChainArgs* dargs = static_cast<stdk::ChainArgs*>(ws.ptr);
-  int* dmap = reinterpret_cast<int*>(static_cast<char*>(ws.ptr) + ((sizeof(stdk::ChainArgs) * n + 255) & ~(size_t)255));
+  int* dlist = reinterpret_cast<int*>(static_cast<char*>(ws.ptr) + args_bytes);
+  unsigned* dflags = reinterpret_cast<unsigned*>(static_cast<char*>(ws.ptr) + args_bytes + list_bytes);
   std::vector<stdk::ChainArgs> args((size_t)n);
-  std::vector<stdecomp_epoch_stats> acc((size_t)n);
+  std::vector<int> nseg_host;
   int rc = STD_OK;
   auto hipck = [&](hipError_t e, const char* what) {
     if (e != hipSuccess && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return e == hipSuccess;
   };
-  if (hipck(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, h0->stream),
-            "batched launch map")) {
-    for (int e = 0; e < n_epochs && rc == STD_OK; ++e) {
-      for (int i = 0; i < n && rc == STD_OK; ++i) {
+  for (int i = 0; i < n && rc == STD_OK; ++i) {
+    stdecomp_handle* h = hs[i];
+    if (h->sched_epoch != h->epoch) rc = run_schedule(h, h->epoch);
+    if (rc == STD_OK) hipck(hipStreamSynchronize(h->stream), "schedule");
+  }
+  if (rc != STD_OK) return rc;
+  hipck(hipMemcpyAsync(dlist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, h0->stream),
+        "batched launch lists");
+  for (int i = 0; i < n; ++i) {
+    hipck(hipMemsetAsync(hs[i]->err, 0, sizeof(int), h0->stream), "memset");
+    hipck(hipMemsetAsync(hs[i]->nf, 0xFF, sizeof(unsigned long long), h0->stream), "memset");
+  }
+  hipck(hipEventRecord(h0->ev[1], h0->stream), "event");
+  int64_t launches = 0;
+  for (int64_t off = 0; off < max_len && rc == STD_OK; off += kBatchesPerLaunch) {
+    for (int q = 0; q < nslots; ++q) {
+      unsigned passed = 0;  // barriers the slot's flags count before each of its chains
+      for (int i : slot_models[q]) {
         stdecomp_handle* h = hs[i];
-        if (h->sched_epoch != h->epoch) rc = run_schedule(h, h->epoch);
-        if (rc == STD_OK) hipck(hipStreamSynchronize(h->stream), "schedule");
-      }
-      if (rc != STD_OK) break;
-      hipck(hipEventRecord(h0->ev[1], h0->stream), "event");
-      for (int64_t c0 = 0; c0 < max_nb && rc == STD_OK; c0 += kBatchesPerLaunch) {
-        for (int i = 0; i < n; ++i) {
-          stdecomp_handle* h = hs[i];
-          args[i] = chain_args(h);
-          args[i].b_begin = c0 < h->nb ? c0 : h->nb;
-          args[i].b_end = c0 + kBatchesPerLaunch < h->nb ? c0 + kBatchesPerLaunch : h->nb;
-          hipck(hipMemsetAsync(h->err, 0, sizeof(int), h0->stream), "memset");
-          if (c0 == 0) hipck(hipMemsetAsync(h->nf, 0xFF, sizeof(unsigned long long), h0->stream), "memset");
-          hipck(hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h0->stream), "memset");
-        }
-        hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
-              "batched launch arguments");
-        hipck(stdk::launch_chain_multi(h0->s, h0->dtype == STD_DTYPE_BF16, dargs, dmap, total_w, h0->threads, lds,
-                                       h0->stream),
-              "batched chain launch");
-        hipck(hipStreamSynchronize(h0->stream), "batched chain launch");  // (args reused next)
-      }
-      hipck(hipEventRecord(h0->ev[2], h0->stream), "event");
-      hipck(hipStreamSynchronize(h0->stream), "event");
-      float ms = 0.f;
-      hipck(hipEventElapsedTime(&ms, h0->ev[1], h0->ev[2]), "event");
-      for (int i = 0; i < n && rc == STD_OK; ++i) {
-        stdecomp_handle* h = hs[i];
-        int err = 0;
-        unsigned long long nf = ~0ull;
-        hipck(hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h0->stream), "error flag");
-        hipck(hipMemcpyAsync(&nf, h->nf, sizeof(nf), hipMemcpyDeviceToHost, h0->stream), "non-finite record");
-        hipck(hipStreamSynchronize(h0->stream), "error flag");
-        if (err && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
-        if (nf != ~0ull && rc == STD_OK) {
-          diverged_at(h, h->epoch, nf);
-          rc = fail(h0, STD_E_DIVERGED, "model " + std::to_string(i) + ": " + h->last_error);
-        }
-        acc[i].epochs_run++;
-        acc[i].updates += h->T;
-        acc[i].minibatches += h->nb;
-        acc[i].chain_seconds += ms * 1e-3;  // (the whole batched launch)
-        acc[i].device_seconds += ms * 1e-3;
-        acc[i].chain_launches += (max_nb + kBatchesPerLaunch - 1) / kBatchesPerLaunch;
-        acc[i].flops_alg += (double)h->T * (2.0 * h->s.N + 4.0) * h->s.P;
-        h->epoch++;
+        stdk::ChainArgs& a = args[i];
+        a = chain_args(h);
+        a.b_begin = std::min(b0[i] + off, b1[i]);
+        a.b_end = std::min(b0[i] + off + kBatchesPerLaunch, b1[i]);
+        a.bar = dflags + (size_t)q * W * stdk::kFlagStride;
+        a.passed0 = passed;
+        a.jv = stdk::chain_variant(h->s);
+        passed += (unsigned)((a.b_end - a.b_begin) * (h->s.N + 1 + (h->lay.core2 ? 1 : 0)));
       }
     }
+    hipck(hipMemsetAsync(dflags, 0, flag_bytes, h0->stream), "memset");
+    hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
+          "batched launch arguments");
+    hipck(stdk::launch_chain_queue(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, dargs, dlist, nslots, W, h0->threads,
+                                   lds, h0->stream),
+          "batched chain launch");
+    hipck(hipStreamSynchronize(h0->stream), "batched chain launch");  // (args reused next)
+    ++launches;
   }
-  if (rc) return rc;
+  hipck(hipEventRecord(h0->ev[2], h0->stream), "event");
+  hipck(hipStreamSynchronize(h0->stream), "event");
+  float ms = 0.f;
+  hipck(hipEventElapsedTime(&ms, h0->ev[1], h0->ev[2]), "event");
+  for (int i = 0; i < n && rc == STD_OK; ++i) {
+    stdecomp_handle* h = hs[i];
+    int err = 0;
+    unsigned long long nf = ~0ull;
+    nseg_host.resize((size_t)h->nb * h->s.N);
+    const size_t N = (size_t)h->s.N;
+    hipck(hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h0->stream), "error flag");
+    hipck(hipMemcpyAsync(&nf, h->nf, sizeof(nf), hipMemcpyDeviceToHost, h0->stream), "non-finite record");
+    if (b1[i] > b0[i])  // (the segment counts of the minibatches run)
+      hipck(hipMemcpyAsync(nseg_host.data() + b0[i] * N, h->nseg + b0[i] * N, (size_t)(b1[i] - b0[i]) * N * 4,
+                           hipMemcpyDeviceToHost, h0->stream),
+            "segment counts");
+    hipck(hipStreamSynchronize(h0->stream), "error flag");
+    if (err && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
+    if (nf != ~0ull && rc == STD_OK) {
+      diverged_at(h, h->epoch, nf);
+      rc = fail(h0, STD_E_DIVERGED, "model " + std::to_string(i) + ": " + h->last_error);
+    }
+    acc[i].chain_seconds += ms * 1e-3;  // (the whole batched launch)
+    acc[i].device_seconds += ms * 1e-3;
+    acc[i].chain_launches += launches;
+    add_work(h, b0[i], b1[i], nseg_host, &acc[i]);
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stdecomp_epoch_batched(stdecomp_handle* const* hs, int32_t n, int32_t n_epochs, stdecomp_epoch_stats* st) {
+  if (!hs || n < 1) return STD_E_INVAL;
+  for (int i = 0; i < n; ++i)
+    if (!hs[i]) return STD_E_STATE;
+  stdecomp_handle* h0 = hs[0];
+  if (n_epochs < 0) return fail(h0, STD_E_INVAL, "n_epochs < 0");
+  for (int i = 0; i < n; ++i)
+    if (hs[i]->cursor != 0)
+      return fail(h0, STD_E_STATE, "model " + std::to_string(i) + " is inside an epoch (stdecomp_step_batched)");
+  size_t lds = 0;
+  if (!batch_compatible(hs, n, &lds)) {  // the same updates, one handle after another
+    for (int i = 0; i < n; ++i) {
+      int rc = stdecomp_epoch(hs[i], n_epochs, st ? &st[i] : nullptr);
+      if (rc) return rc;
+    }
+    return STD_OK;
+  }
+  std::vector<stdecomp_epoch_stats> acc((size_t)n);
+  for (auto& x : acc) x.train_rmse = std::nan("");
+  std::vector<int64_t> b0((size_t)n, 0), b1((size_t)n);
+  for (int i = 0; i < n; ++i) b1[i] = hs[i]->nb;
+  for (int e = 0; e < n_epochs; ++e) {
+    int rc = run_batched_ranges(hs, n, lds, b0, b1, acc);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+      acc[i].epochs_run++;
+      hs[i]->epoch++;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (st) st[i] = acc[i];
+    int r2 = check_finite(hs[i]);
+    if (r2) return r2;
+  }
+  return STD_OK;
+}
+
+int stdecomp_step_batched(stdecomp_handle* const* hs, int32_t n, int64_t max_minibatches, stdecomp_epoch_stats* st) {
+  if (!hs || n < 1) return STD_E_INVAL;
+  for (int i = 0; i < n; ++i)
+    if (!hs[i]) return STD_E_STATE;
+  stdecomp_handle* h0 = hs[0];
+  if (max_minibatches < 1) return fail(h0, STD_E_INVAL, "max_minibatches < 1");
+  std::vector<stdecomp_epoch_stats> acc((size_t)n);
+  for (auto& x : acc) x.train_rmse = std::nan("");
+  std::vector<int64_t> b0((size_t)n), b1((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    b0[i] = hs[i]->cursor;
+    b1[i] = std::min(hs[i]->nb, b0[i] + max_minibatches);
+  }
+  size_t lds = 0;
+  if (batch_compatible(hs, n, &lds)) {
+    int rc = run_batched_ranges(hs, n, lds, b0, b1, acc);
+    if (rc) return rc;
+  } else {  // the same updates, one handle after another
+    std::vector<int> nseg_host;
+    for (int i = 0; i < n; ++i) {
+      int rc = run_range(hs[i], hs[i]->epoch, b0[i], b1[i], &acc[i], nseg_host);
+      if (rc) return rc;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    stdecomp_handle* h = hs[i];
+    h->cursor = b1[i];
+    if (h->cursor == h->nb) {
+      h->cursor = 0;
+      h->epoch++;
+      acc[i].epochs_run++;
+    }
+  }
   for (int i = 0; i < n; ++i) {
     if (st) st[i] = acc[i];
     int r2 = check_finite(hs[i]);
@@ -966,21 +1136,23 @@ int stdecomp_predict(stdecomp_handle* h, int64_t q, const int32_t* idx, float* o
   if (q < 0 || (q > 0 && (!idx || !out))) return fail(h, STD_E_INVAL, "bad predict arguments");
   if (q == 0) return STD_OK;
   uint32_t* rec = nullptr;
-  int rc = pack_caller_entries(h, q, idx, nullptr, on_device, &rec);
+  // (on the handle's query stream, with its own flag: this may run while
+  // another thread trains the handle on its main stream)
+  const hipStream_t qs = h->qstream;
+  int rc = pack_caller_entries(h, q, idx, nullptr, on_device, &rec, qs, h->qflag);
   if (rc) return rc;
   float* dout = out;
   if (!on_device) {
-    if ((rc = dalloc(h, &dout, (size_t)q))) {
-      dfree(h, rec);
+    if ((rc = dalloc(h, &dout, (size_t)q, false, qs))) {
+      dfree(h, rec, qs);
       return rc;
     }
-    h->device_bytes -= (size_t)q * 4;
   }
-  hipError_t e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->stream);
-  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  dfree(h, rec);
-  if (!on_device) dfree(h, dout);
+  hipError_t e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), qs);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, qs);
+  if (e == hipSuccess) e = hipStreamSynchronize(qs);
+  dfree(h, rec, qs);
+  if (!on_device) dfree(h, dout, qs);
   if (e != hipSuccess) return hip_fail(h, e, "predict");
   return STD_OK;
 }
@@ -1012,20 +1184,20 @@ int stdecomp_predict_noalloc(stdecomp_handle* h, int64_t q, const int32_t* idx, 
         if (v < 0 || v >= h->s.I[k]) return fail(h, STD_E_INVAL, "index out of range");
       }
     int32_t* sidx = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(base) + rec_bytes);
-    HIPCHK(h, hipMemcpyAsync(sidx, idx, (size_t)q * N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(sidx, idx, (size_t)q * N * 4, hipMemcpyHostToDevice, h->qstream));
     didx = sidx;
     dout = reinterpret_cast<float*>(static_cast<unsigned char*>(base) + rec_bytes + idx_bytes);
   }
   int bad = 0;
-  hipError_t e = stdk::launch_fill_i32(h->flag, 0, 1, h->stream);
-  if (e == hipSuccess) e = stdk::launch_pack_records(h->s, didx, nullptr, q, rec, h->flag, h->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  hipError_t e = stdk::launch_fill_i32(h->qflag, 0, 1, h->qstream);
+  if (e == hipSuccess) e = stdk::launch_pack_records(h->s, didx, nullptr, q, rec, h->qflag, h->qstream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, h->qflag, sizeof(int), hipMemcpyDeviceToHost, h->qstream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->qstream);
   if (e != hipSuccess) return hip_fail(h, e, "predict_noalloc: packing entries");
   if (bad) return fail(h, STD_E_INVAL, "index out of range");
-  e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->stream);
-  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  e = stdk::launch_predict(h->s, rec, q, factor_ptrs(h), h->G, dout, eval_blocks(h, q), h->qstream);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, (size_t)q * 4, hipMemcpyDeviceToHost, h->qstream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->qstream);
   if (e != hipSuccess) return hip_fail(h, e, "predict_noalloc");
   return STD_OK;
 }
@@ -1041,7 +1213,7 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
     use = h->coo;
   } else {
     if (n < 1 || !idx || !vals) return fail(h, STD_E_INVAL, "bad loss arguments");
-    int rc = pack_caller_entries(h, n, idx, vals, on_device, &rec);
+    int rc = pack_caller_entries(h, n, idx, vals, on_device, &rec, h->stream, h->flag);
     if (rc) return rc;
     use = rec;
   }
@@ -1161,6 +1333,7 @@ int stdecomp_set_epoch(stdecomp_handle* h, int64_t e) {
   if (!h) return STD_E_STATE;
   if (e < 0) return fail(h, STD_E_INVAL, "negative epoch");
   h->epoch = e;
+  h->cursor = 0;
   return STD_OK;
 }
 
@@ -1196,14 +1369,14 @@ int stdecomp_debug_schedule(stdecomp_handle* h, int64_t epoch, int64_t batch, in
   const int m = (int)((h->T - base < h->M) ? h->T - base : h->M);
   int64_t* dperm = nullptr;
   int32_t *doff = nullptr, *drow = nullptr, *dn = nullptr;
-  if ((rc = dalloc(h, &dperm, (size_t)h->T)) || (rc = dalloc(h, &doff, (size_t)m + 1)) ||
-      (rc = dalloc(h, &drow, (size_t)m)) || (rc = dalloc(h, &dn, 1))) {
+  if ((rc = dalloc(h, &dperm, (size_t)h->T, false)) || (rc = dalloc(h, &doff, (size_t)m + 1, false)) ||
+      (rc = dalloc(h, &drow, (size_t)m, false)) || (rc = dalloc(h, &dn, 1, false))) {
     dfree(h, dperm);
     dfree(h, doff);
     dfree(h, drow);
     return rc;
   }
-  h->device_bytes -= (size_t)h->T * 8 + (size_t)(2 * m + 2) * 4;
+
   std::vector<uint16_t> sig(m);
   hipError_t e = stdk::launch_perm_only(h->T, h->seed_sample, epoch, dperm, h->stream);
   if (e == hipSuccess)
@@ -1258,12 +1431,14 @@ int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out) {
   out->device_bytes = (int64_t)h->device_bytes;
   out->minibatches = h->nb;
   out->epoch = h->epoch;
+  out->cursor = h->cursor;
   return STD_OK;
 }
 
 int stdecomp_free(stdecomp_handle* h) {
   if (!h) return STD_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->qstream) (void)hipStreamSynchronize(h->qstream);
   release(h);
   delete h;
   return STD_OK;

@@ -130,3 +130,49 @@ def test_sample_order_on_device_and_stream(lib, oracle_mod):
     np.testing.assert_array_equal(got_dev.cpu().numpy(), want)
     np.testing.assert_array_equal(lib.sample_order(T, seed, epoch), want)
     np.testing.assert_array_equal(lib.sample_order(T, seed, epoch, device=True).cpu().numpy(), want)
+
+
+def test_predict_while_training(lib):
+    """Predictions from one thread while another trains the same handle:
+    they run on the handle's query stream (through the entry point that
+    allocates nothing: a hipFree would wait for the training launch), return
+    finite values, several of them complete while the epochs run, and the
+    training ends bit for bit where it ends with no queries."""
+    import threading
+    dims, ranks = (3000, 2000, 1000), (8, 8, 8)
+    idx, vals = synth.random_tiny(3, dims, ranks, 400000, seed=87, skew=1.1)
+    A0, G0 = synth.init_params(dims, ranks, seed=88)
+    ref = _model(lib, dims, ranks, idx, vals, A0, G0)
+    ref.epoch(3)
+    want = ref.get_params()
+    ref.close()
+    h = _model(lib, dims, ranks, idx, vals, A0, G0)
+    done = threading.Event()
+    err = []
+
+    def train():
+        try:
+            h.epoch(3)
+        except Exception as e:  # reported below
+            err.append(e)
+        done.set()
+
+    th = threading.Thread(target=train)
+    rng = np.random.default_rng(89)
+    th.start()
+    calls = 0
+    while not done.is_set() or calls == 0:
+        q = np.stack([rng.integers(0, I, 2000) for I in dims]).astype(np.int32)
+        out = h.predict_noalloc(q)
+        assert np.all(np.isfinite(out))
+        calls += 1
+    th.join()
+    assert not err, err
+    say("predictions during training:", calls, "calls")
+    # the predictions ran beside the training launch, not after it
+    assert calls >= 3, calls
+    got = h.get_params()
+    for a, b in zip(want[0], got[0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(want[1], got[1])
+    h.close()

@@ -447,14 +447,24 @@ def test_rows_after_minibatches(lib, oracle_mod, dims, ranks, chunk, M):
 
 # ------------------------------------------------ several models, one launch
 # stdecomp_epoch_batched runs the chains of independent models in one
-# launch; every model must end exactly where it ends alone (the same chain
-# code, arguments and workgroup count), and a batch the single launch cannot
-# take (mixed ranks) falls back to running the models one after another.
+# launch, slots of W workgroups each running a balanced list of chains; every
+# model must end exactly where it ends alone (the same chain body, arguments
+# and workgroup count), and a batch the single launch cannot take (different
+# workgroup counts) falls back to running the models one after another.
 BATCH_SETS = {
-    "n3_j4": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((120, 90, 60), (4, 4, 4), 9000, 256, 32),
-              ((300, 40, 70), (4, 4, 4), 15000, 1024, 128), ((50, 50, 50), (4, 4, 4), 3000, 128, 64)],
-    "n4_j8": [((60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 64), ((40, 30, 20, 15), (8, 8, 8, 8), 8000, 512, 128)],
-    "mixed_ranks_fallback": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((80, 70, 60), (5, 5, 5), 6000, 256, 64)],
+    # (dims, ranks, nnz, M, chunk): one launch needs the same workgroup count W = ceil(M / chunk)
+    "n3_j4_w8": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((120, 90, 60), (4, 4, 4), 9000, 256, 32),
+                 ((300, 40, 70), (4, 4, 4), 15000, 1024, 128), ((50, 50, 50), (4, 4, 4), 3000, 128, 16)],
+    "n3_mixed_ranks_w8": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((80, 70, 60), (5, 5, 5), 6000, 256, 32),
+                          ((100, 90, 80), (8, 8, 8), 8000, 512, 64), ((60, 50, 40), (16, 16, 16), 5000, 512, 64),
+                          ((70, 60, 50), (3, 4, 6), 4000, 128, 16)],
+    # W = 64: four slots of the device's compute units, seven chains, so slots run chains one after another
+    "n3_more_chains_than_slots_w64": [((200, 150, 100), (4, 4, 4), 20000, 512, 8), ((120, 90, 60), (8, 8, 8), 9000, 512, 8),
+                                      ((300, 40, 70), (4, 4, 4), 15000, 512, 8), ((50, 50, 50), (3, 3, 3), 3000, 512, 8),
+                                      ((90, 80, 70), (5, 5, 5), 7000, 512, 8), ((40, 30, 20), (4, 4, 4), 2000, 512, 8),
+                                      ((110, 100, 90), (6, 6, 6), 11000, 512, 8)],
+    "n4_j8_w16": [((60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 64), ((40, 30, 20, 15), (8, 8, 8, 8), 8000, 512, 32)],
+    "different_w_fallback": [((200, 150, 100), (4, 4, 4), 20000, 512, 64), ((80, 70, 60), (5, 5, 5), 6000, 256, 64)],
 }
 
 
@@ -482,6 +492,8 @@ def test_batched_models_match_alone(lib, oracle_mod, name, dtype):
     tol = TOL if dtype == "f32" else BF16_TOL
     for e in range(2):
         stats = lib.epoch_batched(hs, 1)
+        if not name.endswith("fallback"):  # one launch: every model reports the same launch time
+            assert len({s["chain_seconds"] for s in stats}) == 1, stats
         mixed = [h.get_params() for h in hs]
         for k, ((dims, ranks, idx, vals, _, _, M, _), (As, Gs_), (Ag, Gg), s) in enumerate(
                 zip(inputs, starts, mixed, stats)):
@@ -499,6 +511,51 @@ def test_batched_models_match_alone(lib, oracle_mod, name, dtype):
         diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A1, A2)] + [float(np.max(np.abs(G1 - G2)))])
         say("  model", k, "max |alone - batched|", diff)
         assert diff == 0.0, (k, diff)
+
+
+@pytest.mark.parametrize("name", ["n3_mixed_ranks_w8", "different_w_fallback"])
+def test_step_batched_windows_match_whole_epochs(lib, name):
+    """Continuous batching: advancing the models by windows of 7 minibatches
+    (models joining the batch at different times, finishing their epochs at
+    different windows) ends every model bit for bit where two whole epochs
+    alone end; a model inside an epoch refuses stdecomp_epoch."""
+    models = BATCH_SETS[name]
+    say("windows", name)
+    inputs = []
+    for k, (dims, ranks, nnz, M, chunk) in enumerate(models):
+        idx, vals = synth.random_tiny(len(dims), dims, ranks, nnz, seed=40 + k, skew=1.2)
+        A0, G0 = synth.init_params(dims, ranks, seed=50 + k)
+        inputs.append((dims, ranks, idx, (vals * 0.5).astype(np.float32), A0, G0, M, chunk))
+    alone = []
+    for (dims, ranks, idx, vals, A0, G0, M, chunk) in inputs:
+        h = make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.02, seed=77, chunk=chunk)
+        h.epoch(2)
+        alone.append(h.get_params())
+        h.close()
+    hs = [make_handle(lib, dims, ranks, idx, vals, A0, G0, M, lr=0.02, seed=77, chunk=chunk)
+          for (dims, ranks, idx, vals, A0, G0, M, chunk) in inputs]
+    joined, calls = 1, 0
+    while True:
+        active = [h for h in hs[:joined] if h.info()["epoch"] < 2]
+        if not active and joined >= len(hs):
+            break
+        if active:
+            lib.step_batched(active, 7)
+        calls += 1
+        if calls == 1:  # the first model is 7 minibatches into its first epoch
+            with pytest.raises(lib.StdecompError) as ei:
+                hs[0].epoch(1)
+            assert ei.value.code == lib.STD_E_STATE
+        if calls % 2 == 0 and joined < len(hs):  # one more model joins every second window
+            joined += 1
+    say("  windows:", calls)
+    for k, (h, (A1, G1)) in enumerate(zip(hs, alone)):
+        assert h.info()["epoch"] == 2 and h.info()["cursor"] == 0
+        A2, G2 = h.get_params()
+        diff = max([float(np.max(np.abs(a - b))) for a, b in zip(A1, A2)] + [float(np.max(np.abs(G1 - G2)))])
+        say("  model", k, "max |alone - windows|", diff)
+        assert diff == 0.0, (k, diff)
+        h.close()
 
 
 def test_serving_loop_results_match_alone(lib, oracle_mod):
