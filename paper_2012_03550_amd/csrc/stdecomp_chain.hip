@@ -1366,13 +1366,16 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
           g[r1 * ke + c1] = wt[r1 <= c1 ? tri_index(r1, c1, ke) : tri_index(c1, r1, ke)];
     }
     __syncthreads();
-    // 5. the column steps, c = 0 .. R-1 in order: row a of V_c by a group of
-    //    tpr lanes (a power of two within one wave), summed by xor shuffles
-    {
+    // 5. the column steps, c = 0 .. R-1 in order, by wave 0 alone: row a of
+    //    V_c by a group of tpr lanes (a power of two), summed by xor shuffles.
+    //    Within one wave LDS operations complete in program order, so every
+    //    lane's read of b_c precedes the write of its new value, and that
+    //    write precedes the next column's reads; no workgroup barrier is needed.
+    if (wv == 0) {
       float* Bn = Bs + L.kboff[n];
       int tpr = 64;
-      while (tpr > 1 && tpr * Jn > BT) tpr >>= 1;
-      const int ra = tid / tpr, l = tid % tpr;
+      while (tpr > 1 && tpr * Jn > 64) tpr >>= 1;
+      const int ra = lane / tpr, l = lane % tpr;
       for (int c = 0; c < R; ++c) {
         float V = 0.f;
         if (ra < Jn) {
@@ -1388,31 +1391,40 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
           V -= g[(c * Jn + ra) * ke + E];  // - (W_c^T x)[a]
           old = Bn[ra * R + c];
         }
-        __syncthreads();  // every group has read b_c
         if (ra < Jn && l == 0) {
           const float nb = old - a.gG * (V * inv_m + a.lG * old);
           Bn[ra * R + c] = nb;
           if (!__builtin_isfinite(nb)) report_nonfinite(a, nf_key(b, 0, L.kboff[n] + ra * R + c));
         }
-        __syncthreads();
       }
     }
+    __syncthreads();
   }
-  // 6. the core of the updated B: G[lin] = sum_r prod_k B(k)[j_k, r]
-  float* Gs = lds + L.gs;
-  for (int lin = tid; lin < s.P; lin += BT) {
-    int jo[kMaxOrder];
-#pragma unroll
-    for (int k = 0; k < kMaxOrder; ++k) jo[k] = k < N ? L.kboff[k] + ((lin / s.lstride[k]) % s.J[k]) * R : 0;
-    float acc = 0.f;
-    for (int r = 0; r < R; ++r) {
+  // 6. the core of the updated B, G[lin] = sum_r prod_k B(k)[j_k, r], by
+  //    halves of the modes: Lf[jl][r] = prod_{k < h} B(k)[j_k, r] and
+  //    Rf[jr][r] = prod_{k >= h} B(k)[j_k, r] (in the [W | x] region), then
+  //    G[jl + PL jr] = sum_r Lf[jl][r] Rf[jr][r]
+  {
+    float* Gs = lds + L.gs;
+    const int h = N >> 1, PL = s.lstride[h], PR = s.P / PL;
+    float* Lf = wt;
+    float* Rf = wt + PL * R;
+    for (int e = tid; e < (PL + PR) * R; e += BT) {
+      const bool left = e < PL * R;
+      const int e2 = left ? e : e - PL * R;
+      const int jx = e2 / R, r = e2 - jx * R;
+      const int lin = left ? jx : jx * PL;
       float t = 1.f;
-#pragma unroll
-      for (int k = 0; k < kMaxOrder; ++k)
-        if (k < N) t *= Bs[jo[k] + r];
-      acc += t;
+      for (int k = left ? 0 : h; k < (left ? h : N); ++k) t *= Bs[L.kboff[k] + ((lin / s.lstride[k]) % s.J[k]) * R + r];
+      wt[e] = t;
     }
-    Gs[lin] = acc;
+    __syncthreads();
+    for (int lin = tid; lin < s.P; lin += BT) {
+      const int jr = lin / PL, jl = lin - jr * PL;
+      float acc = 0.f;
+      for (int r = 0; r < R; ++r) acc = fmaf(Lf[jl * R + r], Rf[jr * R + r], acc);
+      Gs[lin] = acc;
+    }
   }
   __syncthreads();
   return true;
@@ -2027,8 +2039,11 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     for (int n = 0; n < N; ++n) e = std::max(e, nwb * mt[n].hpt * s.J[n]);
     L.es = e + 1 + (e & 1);  // odd, > e
   }
-  L.ras = pad4(JR) + 1;
-  L.sstride = 4 + pad4(JR);
+  // (sized by the largest rank, not the kernel's register bound: the generic
+  // kernels read at most J_max values of a split-row entry, and the core GEMM
+  // reads rows j0 >= J_0 of r a(0) only into output rows it does not store)
+  L.ras = pad4(jmax) + 1;
+  L.sstride = 4 + pad4(jmax);
   L.wstride = pad4(JR) + 4;
   {  // two-level core update when every workgroup summing all partials would cost more than a barrier
     const int P4 = pad4(s.P) / 4;
@@ -2056,7 +2071,9 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
     L.ke = a.R * jmax + 1;
     L.kws = ((L.ke + 15) & ~15) + 1;  // whole 16-column tiles, odd stride
     L.klg = (L.ke * (L.ke + 1)) / 2;
-    const size_t need = al(std::max((size_t)L.chp * L.kws, (size_t)L.klg)) +
+    const int PL = s.lstride[N / 2];
+    const size_t halves = (size_t)(PL + s.P / PL) * a.R;  // the two half-products of forming G
+    const size_t need = al(std::max(std::max((size_t)L.chp * L.kws, (size_t)L.klg), halves)) +
                         al(std::max((size_t)L.ke * L.ke, (size_t)threads));
     const size_t have = al((size_t)khimax * L.hs) + al((size_t)L.chp * L.es) + al((size_t)L.chp * L.ras);
     kr_extra = need > have ? need - have : 0;
@@ -2080,7 +2097,8 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
   L.ebuf = (int)off;  off += al((size_t)L.chp * L.es);
   L.ra = (int)off;    off += al((size_t)L.chp * L.ras) + kr_extra;
   L.kwt = L.hp;
-  L.kg = L.hp + (int)al(std::max((size_t)L.chp * L.kws, (size_t)L.klg));
+  L.kg = L.hp + (int)al(std::max(std::max((size_t)L.chp * L.kws, (size_t)L.klg),
+                                   a.R > 0 ? (size_t)(s.lstride[N / 2] + s.P / s.lstride[N / 2]) * a.R : (size_t)0));
   L.kb = (int)off;    off += kb_len;
   L.split = (int)off; off += al((size_t)a.split_cap * L.sstride);
   L.cbuf = (int)off;  off += al(a.W > 1 ? (size_t)a.W * 2 * a.carry_stride : 0);

@@ -165,6 +165,7 @@ __device__ __forceinline__ void gather_rows(const Shape& s, float* const* A, con
     case 10: { constexpr int JU = 10; CALL; } break; \
     case 12: { constexpr int JU = 12; CALL; } break; \
     case 16: { constexpr int JU = 16; CALL; } break; \
+    case 20: { constexpr int JU = 20; CALL; } break; \
     default: { constexpr int JU = 0; CALL; } break;  \
   }
 

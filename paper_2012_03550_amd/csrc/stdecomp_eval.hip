@@ -18,7 +18,7 @@ int chain_variant(const Shape& s) {
   for (int k = 1; k < s.N; ++k)
     if (s.J[k] != j0) return 0;
   switch (j0) {
-    case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 16: return j0;
+    case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 16: case 20: return j0;
     default: return 0;
   }
 }

@@ -148,7 +148,8 @@ struct ChainArgs {
 };
 
 // Which J specialisation of the chain serves a shape: the common rank when
-// every mode has the same J_n <= 16, else 0 (generic, J_n <= 32).
+// every mode has the same J_n in {2, 3, 4, 5, 6, 8, 10, 12, 16, 20}, else 0
+// (generic, J_n <= 32).
 int chain_variant(const Shape& s);
 
 // Kernel launchers (stdecomp_kernels.hip).  All return hipError_t values.

@@ -244,6 +244,10 @@ def test_init_rejects_bad_problem(lib):
     idx[1, 5] = 0
     with pytest.raises(lib.StdecompError):
         lib.Stdecomp(dims, (2, 2, 33), idx, vals, batch=16)
+    # a core that does not fit one workgroup's LDS: refused, with the reason
+    with pytest.raises(lib.StdecompError) as ei:
+        lib.Stdecomp((30, 30, 30), (24, 24, 24), idx, vals, batch=4096)
+    assert "LDS" in str(ei.value), str(ei.value)
     with pytest.raises(lib.StdecompError):
         lib.Stdecomp(dims, ranks, idx, vals, batch=0)
 
@@ -261,6 +265,10 @@ CASES = [
     ("n3_j10_w4_ragged", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
     ("n3_j16", (100, 90, 80), (16, 16, 16), 6000, 256, 64, None),
     ("n3_j5_chunk1", (50, 40, 30), (5, 5, 5), 700, 8, 1, 1.5),
+    # rank 20: the generic-rank kernel; at M = 4096 the automatic chunk (64, 64
+    # workgroups) leaves 88 floats of the workgroup's LDS unused
+    ("n3_j20_w4", (100, 90, 80), (20, 20, 20), 6000, 256, 64, None),
+    ("n3_j20_auto_m4096", (400, 300, 200), (20, 20, 20), 2 * 4096 + 100, 4096, 0, 1.2),
 ]
 
 
