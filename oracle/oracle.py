@@ -86,9 +86,17 @@ def lib():
                                       ctypes.c_int64, _i32p, _f32p, ctypes.c_int64, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64p, ctypes.c_uint64,
                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p]
+        L.orc_step_momentum.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, _f64p, _f64p, _f64p, ctypes.c_int64,
+                                        _i32p, _f32p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double]
+        L.orc_run_momentum.argtypes = [ctypes.c_int, _i64p, _i32p, _f64p, _f64p, _f64p, _f64p, ctypes.c_int64,
+                                       _i32p, _f32p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64p, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _i64p]
         for f in ("orc_perm", "orc_segments", "orc_predict", "orc_loss", "orc_core_step",
                   "orc_mode_step", "orc_step", "orc_run", "orc_kruskal_core", "orc_kruskal_W",
-                  "orc_kruskal_column_step", "orc_kruskal_core_step", "orc_step_kruskal", "orc_run_kruskal"):
+                  "orc_kruskal_column_step", "orc_kruskal_core_step", "orc_step_kruskal", "orc_run_kruskal",
+                  "orc_step_momentum", "orc_run_momentum"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -226,6 +234,52 @@ class Model:
         _check(lib().orc_run(*self._args(), T, _ptr(idx, _i32p), _ptr(vals, _f32p), M, gam_A, lam_A,
                              gam_G, lam_G, pp, ctypes.c_uint64(seed), epoch0, n_epochs, max_batches,
                              _ptr(done, _i64p)), "orc_run")
+        return int(done[0])
+
+
+# --------------------------------------------------------- heavy-ball momentum
+class MomentumModel(Model):
+    """The model plus heavy-ball velocities: VA laid out as A (one velocity per
+    factor row, zero at start), VG for the core (orc_step_momentum)."""
+
+    def __init__(self, dims, ranks, A, G, VA=None, VG=None):
+        super().__init__(dims, ranks, A, G)
+        self.flatVA = (np.zeros_like(self.flatA) if VA is None else
+                       np.concatenate([np.ascontiguousarray(v, np.float64).reshape(-1) for v in VA]))
+        self.VG = np.zeros_like(self.G) if VG is None else np.ascontiguousarray(VG, np.float64).reshape(-1).copy()
+
+    @property
+    def VA(self):
+        out, o = [], 0
+        for I, J in zip(self.dims, self.ranks):
+            out.append(self.flatVA[o: o + I * J].reshape(I, J))
+            o += I * J
+        return out
+
+    def _margs(self):
+        return (self.N, _ptr(self.dims, _i64p), _ptr(self.ranks, _i32p), _ptr(self.flatA, _f64p),
+                _ptr(self.G, _f64p), _ptr(self.flatVA, _f64p), _ptr(self.VG, _f64p))
+
+    def step(self, idx, x, gam_A, lam_A, gam_G, lam_G, mu=0.0):
+        idx = np.ascontiguousarray(idx, np.int32)
+        x = np.ascontiguousarray(x, np.float32)
+        _check(lib().orc_step_momentum(*self._margs(), idx.shape[1], _ptr(idx, _i32p), _ptr(x, _f32p),
+                                       gam_A, lam_A, gam_G, lam_G, mu), "orc_step_momentum")
+
+    def run(self, idx, vals, M, gam_A, lam_A, gam_G, lam_G, perm=None, seed=0, epoch0=0,
+            n_epochs=1, max_batches=-1, mu=0.0):
+        idx = np.ascontiguousarray(idx, np.int32)
+        vals = np.ascontiguousarray(vals, np.float32)
+        T = idx.shape[1]
+        pp = None
+        if perm is not None:
+            perm = np.ascontiguousarray(perm, np.int64).reshape(-1)
+            assert perm.size == n_epochs * T
+            pp = _ptr(perm, _i64p)
+        done = np.zeros(1, np.int64)
+        _check(lib().orc_run_momentum(*self._margs(), T, _ptr(idx, _i32p), _ptr(vals, _f32p), M, gam_A, lam_A,
+                                      gam_G, lam_G, mu, pp, ctypes.c_uint64(seed), epoch0, n_epochs, max_batches,
+                                      _ptr(done, _i64p)), "orc_run_momentum")
         return int(done[0])
 
 

@@ -277,9 +277,22 @@ int orc_loss(int N, const int64_t *dims, const int32_t *ranks, const double *A,
 /* with r_p = x_p - x_hat_p from the current A and G.                        */
 /* idx is SoA [N][m] for the m samples of the minibatch.                      */
 /* ------------------------------------------------------------------------ */
+static int core_step_impl(int N, const int64_t *dims, const int32_t *ranks, const double *A,
+                          double *G, int64_t m, const int32_t *idx, const float *x,
+                          double gam_G, double lam_G, double *VG, double mu);
+
 int orc_core_step(int N, const int64_t *dims, const int32_t *ranks, const double *A,
                   double *G, int64_t m, const int32_t *idx, const float *x,
                   double gam_G, double lam_G)
+{
+    return core_step_impl(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G, NULL, 0.0);
+}
+
+/* The same step with heavy-ball momentum when VG is given (see
+ * orc_step_momentum): VG <- mu VG + grad, G <- G - gamma_G VG. */
+static int core_step_impl(int N, const int64_t *dims, const int32_t *ranks, const double *A,
+                          double *G, int64_t m, const int32_t *idx, const float *x,
+                          double gam_G, double lam_G, double *VG, double mu)
 {
     int64_t P, off[ORC_MAXN], i[ORC_MAXN];
     if (check_model(N, dims, ranks, &P) || m < 1) return ORC_EINVAL;
@@ -300,7 +313,12 @@ int orc_core_step(int N, const int64_t *dims, const int32_t *ranks, const double
     }
     for (int64_t lin = 0; lin < P; lin++) {
         double grad = -sum_rh[lin] / (double)m + lam_G * G[lin];
-        G[lin] -= gam_G * grad;
+        if (VG) {
+            VG[lin] = mu * VG[lin] + grad;
+            G[lin] -= gam_G * VG[lin];
+        } else {
+            G[lin] -= gam_G * grad;
+        }
     }
     free(sum_rh);
     return ORC_OK;
@@ -320,9 +338,23 @@ int orc_core_step(int N, const int64_t *dims, const int32_t *ranks, const double
 /* SGD call of Algorithm 1), not the minibatch size of Eq.                    */
 /* Gradient_factor_matrix; rows absent from the minibatch are not touched.   */
 /* ------------------------------------------------------------------------ */
+static int mode_step_impl(int N, const int64_t *dims, const int32_t *ranks, double *A,
+                          const double *G, int64_t m, const int32_t *idx, const float *x,
+                          int n, double gam_A, double lam_A, double *VA, double mu);
+
 int orc_mode_step(int N, const int64_t *dims, const int32_t *ranks, double *A,
                   const double *G, int64_t m, const int32_t *idx, const float *x,
                   int n, double gam_A, double lam_A)
+{
+    return mode_step_impl(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A, NULL, 0.0);
+}
+
+/* The same step with heavy-ball momentum when VA (velocities laid out as A)
+ * is given (see orc_step_momentum): for each sampled row,
+ * v <- mu v + (F/c_i + lambda_A a), a <- a - gamma_A v. */
+static int mode_step_impl(int N, const int64_t *dims, const int32_t *ranks, double *A,
+                          const double *G, int64_t m, const int32_t *idx, const float *x,
+                          int n, double gam_A, double lam_A, double *VA, double mu)
 {
     int64_t P, off[ORC_MAXN], i[ORC_MAXN];
     if (check_model(N, dims, ranks, &P) || m < 1 || n < 0 || n >= N) return ORC_EINVAL;
@@ -368,8 +400,16 @@ int orc_mode_step(int N, const int64_t *dims, const int32_t *ranks, double *A,
             int32_t p = sigma[q];
             for (int jn = 0; jn < Jn; jn++) F[jn] += -r[p] * E[(int64_t)p * Jn + jn];
         }
-        for (int jn = 0; jn < Jn; jn++)
-            a[jn] -= gam_A * (F[jn] / (double)c + lam_A * a[jn]);
+        if (VA) {
+            double *v = VA + off[n] + (int64_t)seg_row[s] * Jn;
+            for (int jn = 0; jn < Jn; jn++) {
+                v[jn] = mu * v[jn] + (F[jn] / (double)c + lam_A * a[jn]);
+                a[jn] -= gam_A * v[jn];
+            }
+        } else {
+            for (int jn = 0; jn < Jn; jn++)
+                a[jn] -= gam_A * (F[jn] / (double)c + lam_A * a[jn]);
+        }
     }
     free(E); free(r); free(rows); free(sigma); free(seg_off); free(seg_row);
     return ORC_OK;
@@ -426,6 +466,67 @@ int orc_run(int N, const int64_t *dims, const int32_t *ranks, double *A, double 
                 bx[p] = vals[t];
             }
             rc = orc_step(N, dims, ranks, A, G, m, bidx, bx, gam_A, lam_A, gam_G, lam_G);
+            done++;
+        }
+    }
+    if (batches_run) *batches_run = done;
+    free(order); free(bidx); free(bx);
+    return rc;
+}
+
+/* ======================================================================== */
+/* Heavy-ball momentum (Section "Conclusion and Future Works" names momentum  */
+/* as an extension of SGD_Tucker without fixing it).                         */
+/* READING: Polyak's heavy ball on each sub-step's stochastic gradient:      */
+/* v <- mu v + g, theta <- theta - gamma v, with the core's velocity VG       */
+/* updated once per minibatch and one velocity per factor row (VA, laid out  */
+/* as A) updated when its row is sampled; like the rows themselves (lazy     */
+/* rows), the velocity of a row absent from a minibatch neither changes nor  */
+/* decays.  mu = 0 is the plain method.                                      */
+/* ======================================================================== */
+int orc_step_momentum(int N, const int64_t *dims, const int32_t *ranks, double *A, double *G,
+                      double *VA, double *VG, int64_t m, const int32_t *idx, const float *x,
+                      double gam_A, double lam_A, double gam_G, double lam_G, double mu)
+{
+    int64_t P;
+    if (check_model(N, dims, ranks, &P) || !VA || !VG || !(mu >= 0.0 && mu < 1.0)) return ORC_EINVAL;
+    int rc = core_step_impl(N, dims, ranks, A, G, m, idx, x, gam_G, lam_G, VG, mu);
+    for (int n = 0; rc == ORC_OK && n < N; n++)
+        rc = mode_step_impl(N, dims, ranks, A, G, m, idx, x, n, gam_A, lam_A, VA, mu);
+    return rc;
+}
+
+/* Epochs as orc_run, each minibatch by orc_step_momentum. */
+int orc_run_momentum(int N, const int64_t *dims, const int32_t *ranks, double *A, double *G,
+                     double *VA, double *VG, int64_t T, const int32_t *idx, const float *vals,
+                     int64_t M, double gam_A, double lam_A, double gam_G, double lam_G, double mu,
+                     const int64_t *perm, uint64_t seed, int64_t epoch0, int64_t n_epochs,
+                     int64_t max_batches, int64_t *batches_run)
+{
+    int64_t P;
+    if (check_model(N, dims, ranks, &P) || T < 1 || M < 1 || n_epochs < 0) return ORC_EINVAL;
+    if (check_indices(N, dims, T, idx)) return ORC_EINVAL;
+    int64_t *order = (int64_t *)malloc((size_t)T * sizeof(int64_t));
+    int32_t *bidx = (int32_t *)malloc((size_t)(N * M) * sizeof(int32_t));
+    float *bx = (float *)malloc((size_t)M * sizeof(float));
+    if (!order || !bidx || !bx) {
+        free(order); free(bidx); free(bx);
+        return ORC_ENOMEM;
+    }
+    int64_t done = 0;
+    int rc = ORC_OK;
+    for (int64_t e = 0; e < n_epochs && rc == ORC_OK; e++) {
+        if (perm) memcpy(order, perm + e * T, (size_t)T * sizeof(int64_t));
+        else orc_perm(T, seed, epoch0 + e, order);
+        for (int64_t b0 = 0; b0 < T && rc == ORC_OK; b0 += M) {
+            if (max_batches >= 0 && done >= max_batches) break;
+            int64_t m = (T - b0 < M) ? (T - b0) : M;
+            for (int64_t p = 0; p < m; p++) {
+                int64_t t = order[b0 + p];
+                for (int k = 0; k < N; k++) bidx[k * m + p] = idx[k * T + t];
+                bx[p] = vals[t];
+            }
+            rc = orc_step_momentum(N, dims, ranks, A, G, VA, VG, m, bidx, bx, gam_A, lam_A, gam_G, lam_G, mu);
             done++;
         }
     }

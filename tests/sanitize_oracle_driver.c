@@ -24,6 +24,10 @@ int orc_run(int N, const int64_t *dims, const int32_t *ranks, double *A, double 
             const float *vals, int64_t M, double gam_A, double lam_A, double gam_G, double lam_G,
             const int64_t *perm, uint64_t seed, int64_t epoch0, int64_t n_epochs, int64_t max_batches,
             int64_t *batches_run);
+int orc_run_momentum(int N, const int64_t *dims, const int32_t *ranks, double *A, double *G, double *VA,
+                     double *VG, int64_t T, const int32_t *idx, const float *vals, int64_t M, double gam_A,
+                     double lam_A, double gam_G, double lam_G, double mu, const int64_t *perm, uint64_t seed,
+                     int64_t epoch0, int64_t n_epochs, int64_t max_batches, int64_t *batches_run);
 int orc_kruskal_core(int N, const int32_t *ranks, int R, const double *B, double *G);
 int orc_run_kruskal(int N, const int64_t *dims, const int32_t *ranks, double *A, int R, double *B, double *G,
                     int64_t T, const int32_t *idx, const float *vals, int64_t M, double gam_A, double lam_A,
@@ -107,6 +111,16 @@ int main(void)
         double *pred = malloc(sizeof(double) * T), loss[4];
         CHECK(orc_predict(N, dims, ranks, A, G, T, idx, pred) == 0 && all_finite(pred, T));
         CHECK(orc_loss(N, dims, ranks, A, G, T, idx, vals, 0.01, 0.01, loss) == 0 && all_finite(loss, 4));
+        /* heavy-ball momentum; mu outside [0, 1) rejected */
+        double *VA = calloc((size_t)nA, sizeof(double)), *VG = calloc((size_t)P, sizeof(double));
+        CHECK(orc_run_momentum(N, dims, ranks, A, G, VA, VG, T, idx, vals, 16, 0.05, 0.01, 0.05, 0.01, 0.9, NULL,
+                               3, 2, 1, -1, &done) == 0);
+        CHECK(done == (T + 15) / 16);
+        CHECK(all_finite(A, nA) && all_finite(G, P) && all_finite(VA, nA) && all_finite(VG, P));
+        CHECK(orc_run_momentum(N, dims, ranks, A, G, VA, VG, T, idx, vals, 16, 0.05, 0.01, 0.05, 0.01, 1.0, NULL,
+                               3, 2, 1, -1, &done) != 0);
+        free(VA);
+        free(VG);
         idx[0] = (int32_t)dims[0]; /* out of range: rejected */
         CHECK(orc_predict(N, dims, ranks, A, G, T, idx, pred) != 0);
         free(pred);

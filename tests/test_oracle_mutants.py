@@ -11,6 +11,7 @@ import subprocess
 import pytest
 
 import tests.test_oracle_kruskal as kpins
+import tests.test_oracle_momentum as mpins
 import tests.test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "stdecomp_oracle.c")
@@ -49,6 +50,16 @@ MUTANTS = {
     "kruskal_vec_order": ("const int64_t v = j[n] + (int64_t)Jn * col;", "const int64_t v = col + K * j[n];"),
     "kruskal_modes_reversed": ("for (int n = 0; n < N && rc == ORC_OK; n++)\n        rc = kruskal_columns(",
                                "for (int n = N - 1; n >= 0 && rc == ORC_OK; n--)\n        rc = kruskal_columns("),
+    # heavy-ball momentum
+    "momentum_row_velocity_not_carried": ("v[jn] = mu * v[jn] + (F[jn] / (double)c + lam_A * a[jn]);",
+                                          "v[jn] = (F[jn] / (double)c + lam_A * a[jn]);"),
+    "momentum_row_normaliser_m": ("v[jn] = mu * v[jn] + (F[jn] / (double)c + lam_A * a[jn]);",
+                                  "v[jn] = mu * v[jn] + (F[jn] / (double)m + lam_A * a[jn]);"),
+    "momentum_row_steps_on_gradient": ("a[jn] -= gam_A * v[jn];",
+                                       "a[jn] -= gam_A * (F[jn] / (double)c + lam_A * a[jn]);"),
+    "momentum_core_velocity_not_carried": ("VG[lin] = mu * VG[lin] + grad;", "VG[lin] = grad;"),
+    "momentum_core_velocity_squared_mu": ("VG[lin] = mu * VG[lin] + grad;", "VG[lin] = mu * mu * VG[lin] + grad;"),
+    "momentum_core_step_sign": ("G[lin] -= gam_G * VG[lin];", "G[lin] += gam_G * VG[lin];"),
     "kruskal_core_not_formed": ("    if (rc == ORC_OK) rc = orc_kruskal_core(N, ranks, R, B, G);\n    return rc;\n}",
                                 "    return rc;\n}"),
 }
@@ -73,6 +84,10 @@ def _pin_calls():
         (kpins.test_core_step_is_cyclic_over_modes_then_columns, {}),
         (kpins.test_matrix_factorisation_exact_kruskal, {}),
         (kpins.test_kruskal_step_then_factor_steps, {}),
+        (mpins.test_mu_zero_is_the_plain_method, {}),
+        (mpins.test_heavy_ball_matrix_factorisation_exact, {}),
+        (mpins.test_heavy_ball_core_exact, {}),
+        (mpins.test_unsampled_rows_keep_row_and_velocity, {}),
     ]
 
 
