@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--rcore", type=int, default=0,
                     help="(c3) 0: dense core; R > 0: the paper's Kruskal core of rank R (the oracle prefix then "
                          "defaults to 2 minibatches, 1 of them timed)")
+    ap.add_argument("--momentum", type=float, default=0.0,
+                    help="(c3) heavy-ball momentum mu in [0, 1) on every sub-step (0: the plain method)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes 5 times (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +215,7 @@ def run_c3(args):
     M, lr, lam, sample = 8192, 0.05, 1e-4, 200_000
     seed_s, seed_i = 3003, 2003
     R = max(0, args.rcore)
+    mu = args.momentum
     prefix = max(0, args.prefix) if (R == 0 or args.prefix != 200) else 2
     cpu_batches = (48 if R == 0 else 1) if args.cpu_batches < 0 else args.cpu_batches
     cpu_batches = min(cpu_batches, prefix) if prefix else cpu_batches
@@ -227,14 +230,14 @@ def run_c3(args):
     for dtype in dtypes:
         h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
                              lam_factor=lam, lam_core=lam, seed_sample=seed_s, seed_init=seed_i, dtype=dtype,
-                             r_core=R)
+                             r_core=R, momentum=mu)
         if A0 is None:
             A0, G0 = h.get_params()
             B0 = h.get_kruskal() if R else None
             if prefix > 0 or cpu_batches > 0:
                 worker = threading.Thread(target=oracle_prefix, daemon=True,
                                           args=(wl, A0, G0, M, lr, lam, seed_s, max(prefix, cpu_batches),
-                                                cpu_batches, s_idx, s_vals, orc, B0))
+                                                cpu_batches, s_idx, s_vals, orc, B0, mu))
                 worker.start()
         info = h.info()
         log("c3 %s chain" % dtype, info)
@@ -246,6 +249,9 @@ def run_c3(args):
         h.set_params(A0, G0)
         if R:
             h.set_kruskal(B0)
+        if mu > 0:  # the velocities start at zero again
+            VA, VG = h.get_velocity()
+            h.set_velocity([np.zeros_like(v) for v in VA], np.zeros_like(VG))
         A1, G1 = h.get_params()
         if not (all(np.array_equal(a, b) for a, b in zip(A0, A1)) and np.array_equal(G0, G1)):
             raise RuntimeError("c3 %s: parameters read back after set_params differ from those set" % dtype)
@@ -311,9 +317,10 @@ def run_c3(args):
            "dtype": dtypes[0], "data": "synthetic",
            "config": {"workload": "planted_powerlaw 100000x100000x1000x100, %d entries (Zipf 1.2 on modes 1-2, "
                                   "uniform on 3-4), planted rank 8^4 + N(0,0.05^2), 10%% held out; J=(8,8,8,8), "
-                                  "M=8192, lr=0.05, lambda=1e-4%s; step = 1 epoch + held-out RMSE" % (
-                                      nnz, "; Kruskal core R=%d" % R if R else ""),
-                      "train_entries": int(wl.nnz), "batch": M, "r_core": R, "chain_workgroups": head["chain_workgroups"],
+                                  "M=8192, lr=0.05, lambda=1e-4%s%s; step = 1 epoch + held-out RMSE" % (
+                                      nnz, "; Kruskal core R=%d" % R if R else "",
+                                      "; heavy-ball momentum mu=%g" % mu if mu > 0 else ""),
+                      "train_entries": int(wl.nnz), "batch": M, "r_core": R, "momentum": mu, "chain_workgroups": head["chain_workgroups"],
                       "chain_chunk": head["chain_chunk"]},
            "heldout_rmse": head["heldout_rmse_per_step"][-1] if head["heldout_rmse_per_step"] else None,
            "roofline": head["roofline"], "precision": precision, "cpu_baseline": cpu}
@@ -322,12 +329,13 @@ def run_c3(args):
     print(json.dumps(out), flush=True)
 
 
-def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out, B0=None):
+def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out, B0=None, mu=0.0):
     """The FP64 oracle on minibatches [0, nb) of epoch 0 from (A0, G0): the
     entries of those minibatches are taken in the oracle's own epoch order
     and run as a tensor of nb * M entries in identity order (the same
     minibatches); the first nb_timed are timed apart.  Fills out['A'],
-    out['G'], out['rmse'] (held-out sample) and out['seconds']."""
+    out['G'], out['rmse'] (held-out sample) and out['seconds'].  mu > 0:
+    with heavy-ball momentum from zero velocities."""
     import numpy as np
     from oracle import oracle
     oracle.build()
@@ -336,7 +344,11 @@ def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out
     idx = np.ascontiguousarray(wl.train_idx[:, order])
     vals = np.ascontiguousarray(wl.train_vals[order])
     del order
-    if B0 is None:
+    kw = {}
+    if mu > 0:
+        ref = oracle.MomentumModel(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
+        kw = {"mu": mu}
+    elif B0 is None:
         ref = oracle.Model(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0], G0.astype(np.float64))
     else:  # the Kruskal core: the model's core is the product of B0
         ref = oracle.KruskalModel(wl.dims, wl.ranks, [a.astype(np.float64) for a in A0],
@@ -345,11 +357,11 @@ def oracle_prefix(wl, A0, G0, M, lr, lam, seed, nb, nb_timed, s_idx, s_vals, out
     log("oracle: running %d minibatches of epoch 0 (%d timed)" % (nb, nb_timed))
     t = time.perf_counter()
     if cut > 0:
-        ref.run(idx[:, :cut], vals[:cut], M, lr, lam, lr, lam, perm=np.arange(cut, dtype=np.int64))
+        ref.run(idx[:, :cut], vals[:cut], M, lr, lam, lr, lam, perm=np.arange(cut, dtype=np.int64), **kw)
     out["seconds"] = time.perf_counter() - t
     if idx.shape[1] > cut:
         rest = idx.shape[1] - cut
-        ref.run(idx[:, cut:], vals[cut:], M, lr, lam, lr, lam, perm=np.arange(rest, dtype=np.int64))
+        ref.run(idx[:, cut:], vals[cut:], M, lr, lam, lr, lam, perm=np.arange(rest, dtype=np.int64), **kw)
     out["rmse"] = ref.loss(s_idx, s_vals)["rmse"]
     out["A"] = [a.copy() for a in ref.A]
     out["G"] = ref.G.copy()
@@ -674,7 +686,7 @@ def stored_traffic(path, dtype, train_entries, batch, info):
 def kernel_source_hash():
     import hashlib
     hsh = hashlib.sha256()
-    for f in ("stdecomp_chain.hip", "stdecomp_device.h", "stdecomp_internal.h"):
+    for f in ("stdecomp_chain_body.h", "stdecomp_chain.hip", "stdecomp_device.h", "stdecomp_internal.h"):
         hsh.update(open(os.path.join(ROOT, "paper_2012_03550_amd", "csrc", f), "rb").read())
     return hsh.hexdigest()[:16]
 

@@ -109,7 +109,17 @@ typedef struct {
   void* alloc_ctx;             /* passed to dev_alloc / dev_free */
   int32_t report_train_rmse;   /* 1: stdecomp_epoch also evaluates the RMSE over Omega after
                                   its last epoch (one pass of the loss kernel over T entries) */
-  int32_t reserved[11];        /* must be zero */
+  float momentum;              /* mu, 0 <= mu < 1: heavy-ball momentum on every sub-step
+                                  (Section "Conclusion and Future Works" names momentum as
+                                  an extension without fixing it): v <- mu v + g,
+                                  theta <- theta - gamma v, one velocity for the core,
+                                  updated once per minibatch, and one per factor row,
+                                  updated only when the row is sampled.  0: the plain
+                                  method, no velocity buffers.  With mu > 0 the handle holds
+                                  velocities of the size of the parameters (zero at init;
+                                  stdecomp_get/set_velocity); the Kruskal core (r_core > 0)
+                                  is refused (STD_E_INVAL) */
+  int32_t reserved[10];        /* must be zero */
 } stdecomp_options;
 
 typedef struct {
@@ -205,6 +215,16 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
  * Errors: STD_E_INVAL for NULL pointers, STD_E_DEVICE if a copy fails. */
 int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G);
 int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G);
+
+/* Heavy-ball velocities (options.momentum > 0): copy them out of / into the
+ * handle (host memory), laid out as the parameters of stdecomp_get_params:
+ * VA[n] points to I_n x J_n row-major floats, VG to prod(J) floats.  They
+ * start at zero; with the parameters they make a checkpoint from which the
+ * run resumes bit for bit.  stdecomp_set_params leaves them as they are.
+ * STD_E_STATE for a handle without momentum, STD_E_INVAL for NULL pointers,
+ * STD_E_DEVICE if a copy fails. */
+int stdecomp_get_velocity(stdecomp_handle* h, float* const* VA, float* VG);
+int stdecomp_set_velocity(stdecomp_handle* h, const float* const* VA, const float* VG);
 
 /* Kruskal core (options.r_core = R > 0): copy the FP32 masters of B(n)
  * (B[n] points to J_n x R row-major floats) out of / into the handle.

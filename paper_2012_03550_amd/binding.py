@@ -40,7 +40,7 @@ class Options(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("r_core", ctypes.c_int32), ("inputs_on_device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("chain_chunk", ctypes.c_int32), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p), ("report_train_rmse", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 11)]
+                ("momentum", ctypes.c_float), ("reserved", ctypes.c_int32 * 10)]
 
 
 class EpochStats(ctypes.Structure):
@@ -76,6 +76,8 @@ SIGNATURES = {
     "stdecomp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "stdecomp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "stdecomp_set_epoch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "stdecomp_get_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "stdecomp_set_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "stdecomp_get_kruskal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "stdecomp_set_kruskal": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "stdecomp_debug_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p,
@@ -203,11 +205,12 @@ class Stdecomp:
 
     def __init__(self, dims, ranks, idx, vals, batch=256, lr_factor=0.01, lr_core=0.01, lam_factor=0.01,
                  lam_core=0.01, seed_sample=0, seed_init=0, init="scaled", dtype="f32", chunk=0, stream=None,
-                 allocator=None, train_rmse=False, r_core=0):
+                 allocator=None, train_rmse=False, r_core=0, momentum=0.0):
         """allocator: None (the library calls hipMalloc) or a TorchAllocator
         (every device buffer of the handle from torch's caching allocator);
         train_rmse: epoch() also reports the RMSE over the training set;
-        r_core: 0 for a dense core, R > 0 for the Kruskal core of rank R."""
+        r_core: 0 for a dense core, R > 0 for the Kruskal core of rank R;
+        momentum: heavy-ball factor mu in [0, 1) (0: the plain method)."""
         L = load()
         self.N = len(dims)
         self.dims = tuple(int(d) for d in dims)
@@ -238,6 +241,7 @@ class Stdecomp:
         opt.report_train_rmse = 1 if train_rmse else 0
         opt.r_core = int(r_core)
         self.r_core = int(r_core)
+        opt.momentum = float(momentum)
         self.allocator = allocator  # kept alive as long as the handle: the library calls it
         if allocator is not None:
             opt.dev_alloc = allocator._alloc
@@ -346,6 +350,20 @@ class Stdecomp:
         G = np.ascontiguousarray(G, np.float32).reshape(-1)
         ptrs = (ctypes.c_void_p * self.N)(*[a.ctypes.data for a in A])
         self._check(load().stdecomp_set_params(self._h, ptrs, _ptr(G)), "stdecomp_set_params")
+
+    def get_velocity(self):
+        """Heavy-ball velocities (laid out as the parameters) of a handle with momentum."""
+        VA = [np.empty((I, J), np.float32) for I, J in zip(self.dims, self.ranks)]
+        VG = np.empty(int(np.prod(self.ranks)), np.float32)
+        ptrs = (ctypes.c_void_p * self.N)(*[a.ctypes.data for a in VA])
+        self._check(load().stdecomp_get_velocity(self._h, ptrs, _ptr(VG)), "stdecomp_get_velocity")
+        return VA, VG
+
+    def set_velocity(self, VA, VG):
+        VA = [np.ascontiguousarray(a, np.float32) for a in VA]
+        VG = np.ascontiguousarray(VG, np.float32).reshape(-1)
+        ptrs = (ctypes.c_void_p * self.N)(*[a.ctypes.data for a in VA])
+        self._check(load().stdecomp_set_velocity(self._h, ptrs, _ptr(VG)), "stdecomp_set_velocity")
 
     def get_kruskal(self):
         """The Kruskal factors B(n) (J_n x R each) of a handle with r_core > 0."""

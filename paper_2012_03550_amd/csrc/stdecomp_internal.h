@@ -62,6 +62,10 @@ struct ChainLayout {
   int kb, kwt, kg, kws, ke;
   int kboff[kMaxOrder];
   int klg;      // floats of the packed triangle for ke columns: ke (ke + 1) / 2
+  // Heavy-ball momentum: vg = the core velocity this workgroup updates (all P
+  // entries with the one-level core update, every workgroup holding the same
+  // copy; its slice of cper float4 with the two-level update).
+  int vg;
 };
 
 // Per-phase constants of the chain, built on the host.  Phase 0 is the core
@@ -125,11 +129,16 @@ struct ChainArgs {
   int Jb[kMaxOrder];        // row stride of the BF16 copies (J_n rounded up to 8)
   int bf16;                 // 1: BF16 operands, FP32 masters and accumulation
   float* G;                 // FP32 master core (P)
+  int mom;                  // 1: heavy-ball momentum (velocities VA, VG, factor mu)
+  float mu;
+  float* VA[kMaxOrder];     // row velocities, laid out as A (momentum)
+  float* VG;                // core velocity (P, momentum)
   int R;                    // Kruskal rank of the core (0: dense core)
   float* B;                 // Kruskal core: FP32 masters of B(k), J_k x R each, back to back (R > 0)
   float* partial;           // [W][pad4(P)] per-workgroup core-gradient partials; Kruskal core:
                             // [2][W][pad4(klg)] Gram partials then [2][pad4(klg)] their sums
-  float* carry;             // [2][W][2][carry_stride] per-chunk run partials and old rows
+  float* carry;             // [2][W * carry_stride] per parity: the straddling runs' partials, old rows
+                            // (and old velocities) of every chunk (layout at finish_split_rows)
   unsigned* bar;            // grid-barrier arrival flags, one per workgroup, kFlagStride apart (zero at launch)
   int* err;                 // set to nonzero by a workgroup that gives up
   unsigned long long* nf;   // earliest non-finite write: nf_key(b, phase, row), all ones if none
@@ -138,7 +147,7 @@ struct ChainArgs {
   float gA, lA, gG, lG;     // learning steps and L2 weights
   int W;                    // workgroups in the chain
   int chunk;                // samples per workgroup per phase (<= blockDim)
-  int carry_stride;         // floats per carry slot
+  int carry_stride;         // floats of carry per chunk: >= 4 + 3 J_max (4 + 4 J_max with momentum), x4
   long long spin_limit;     // barrier give-up bound (iterations)
   unsigned passed0;         // barriers the flags in bar have counted before this chain starts
   int jv;                   // rank variant of the chain body (chain_variant of s)
@@ -174,9 +183,15 @@ hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipSt
 // barriers the slot counted before it).  Every chain has W workgroups, the
 // same order class (three modes or other), the dense core and the same
 // dtype; ranks may differ (each chain runs the body it runs alone).  bytes = the
-// largest LDS plan among them.
-hipError_t launch_chain_queue(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
-                              int threads, size_t bytes, hipStream_t st);
+// largest LDS plan among them.  mom: every chain has heavy-ball momentum (the
+// kernels of stdecomp_chain_mom.hip), else none has.
+hipError_t launch_chain_queue(int n3, int bf, int mom, const ChainArgs* dev_args, const int* dev_list, int nslots,
+                              int W, int threads, size_t bytes, hipStream_t st);
+// The chain kernels with heavy-ball momentum (stdecomp_chain_mom.hip): one
+// chain (a.mom, dense core, plan already checked) and a batch of chains.
+hipError_t launch_chain_mom(const ChainArgs& a, int threads, size_t bytes, hipStream_t st);
+hipError_t launch_chain_queue_mom(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
+                                  int threads, size_t bytes, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,
                                uint32_t* rec, int* bad, hipStream_t st);
 struct FactorPtrs {

@@ -50,6 +50,9 @@ struct stdecomp_handle {
   uint16_t* Ab[kMaxOrder] = {};  // BF16 read copies (BF16 mode)
   int Jb[kMaxOrder] = {};
   float* G = nullptr;
+  float mu = 0;                  // heavy-ball momentum (0: none, no velocity buffers)
+  float* VA[kMaxOrder] = {};     // row velocities, laid out as A
+  float* VG = nullptr;           // core velocity (P)
   int R = 0;             // Kruskal rank of the core (0: dense core)
   float* B = nullptr;    // Kruskal core: B(n), J_n x R each, back to back
   int64_t nB = 0;        // floats of B
@@ -248,10 +251,12 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
     h->split_cap = W > 1 ? W - 1 : 0;
     int jmax = 0;
     for (int n = 0; n < s.N; ++n) jmax = s.J[n] > jmax ? s.J[n] : jmax;
-    h->carry_stride = stdk::pad4(2 + 2 * jmax);
+    // carry of a chunk: two slots (row, count, partial sum), the old row (and old velocity)
+    h->carry_stride = stdk::pad4(4 + (h->mu > 0 ? 4 : 3) * jmax);
     stdk::ChainArgs a{};
     a.s = s;
     a.R = h->R;
+    a.mom = h->mu > 0 ? 1 : 0;
     a.W = W;
     a.chunk = chunk;
     a.split_cap = h->split_cap;
@@ -296,6 +301,10 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.lay = h->lay;
   for (int i = 0; i <= kMaxOrder; ++i) a.pt[i] = h->pt[i];
   a.G = h->G;
+  a.mom = h->mu > 0 ? 1 : 0;
+  a.mu = h->mu;
+  for (int n = 0; n < h->s.N; ++n) a.VA[n] = h->VA[n];
+  a.VG = h->VG;
   a.R = h->R;
   a.B = h->B;
   a.partial = h->partial;
@@ -460,8 +469,10 @@ void release(stdecomp_handle* h) {
   for (int n = 0; n < kMaxOrder; ++n) {
     dfree(h, h->A[n]);
     dfree(h, h->Ab[n]);
+    dfree(h, h->VA[n]);
   }
   dfree(h, h->G);
+  dfree(h, h->VG);
   dfree(h, h->B);
   dfree(h, h->partial);
   dfree(h, h->carry);
@@ -524,8 +535,10 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   if (o->init_kind < STD_INIT_SCALED || o->init_kind > STD_INIT_CALLER) return STD_E_INVAL;
   if (o->dtype != STD_DTYPE_F32 && o->dtype != STD_DTYPE_BF16) return STD_E_INVAL;
   if (o->r_core < 0 || o->r_core > 64) return STD_E_INVAL;
-  for (int i = 0; i < 11; ++i)
+  for (int i = 0; i < 10; ++i)
     if (o->reserved[i] != 0) return STD_E_INVAL;
+  if (!(o->momentum >= 0.f && o->momentum < 1.f)) return STD_E_INVAL;
+  if (o->momentum > 0.f && o->r_core > 0) return STD_E_INVAL;
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr)) return STD_E_INVAL;
   if (o->report_train_rmse != 0 && o->report_train_rmse != 1) return STD_E_INVAL;
   int64_t P = 1;
@@ -592,6 +605,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   h->seed_sample = o->seed_sample;
   h->dtype = o->dtype;
   h->R = o->r_core;
+  h->mu = o->momentum;
   h->nB = 0;
   for (int n = 0; n < N; ++n) h->nB += (int64_t)s.J[n] * h->R;
   if (o->stream) {
@@ -625,11 +639,16 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       (rc = dalloc(h, &h->meta, T * (N + 1))) || (rc = dalloc(h, &h->aux, h->aux_host.size())) ||
       (rc = dalloc(h, &h->nseg, (size_t)h->nb * N)) || (rc = dalloc(h, &h->G, (size_t)P)) ||
       (rc = dalloc(h, &h->partial, partial_floats(h))) || (h->R > 0 && (rc = dalloc(h, &h->B, (size_t)h->nB))) ||
-      (rc = dalloc(h, &h->carry, (size_t)2 * h->W * 2 * h->carry_stride)) ||
+      (rc = dalloc(h, &h->carry, (size_t)2 * h->W * h->carry_stride)) ||
       (rc = dalloc(h, &h->bar, (size_t)h->W * stdk::kFlagStride)) ||
       (rc = dalloc(h, &h->err, 1)) || (rc = dalloc(h, &h->nf, 1)) || (rc = dalloc(h, &h->dscratch, 3 * 4096)) ||
-      (rc = dalloc(h, &h->flag, 1)) || (rc = dalloc(h, &h->qflag, 1)))
+      (rc = dalloc(h, &h->flag, 1)) || (rc = dalloc(h, &h->qflag, 1)) ||
+      (h->mu > 0 && (rc = dalloc(h, &h->VG, (size_t)P))))
     return bail(rc);
+  if (h->mu > 0 && hipMemsetAsync(h->VG, 0, (size_t)P * 4, h->stream) != hipSuccess) {
+    h->last_error = "hipMemset failed";
+    return bail(STD_E_DEVICE);
+  }
   for (int n = 0; n < N; ++n) {
     h->Jb[n] = (s.J[n] + 7) & ~7;
     if (h->dtype == STD_DTYPE_BF16 && (rc = dalloc(h, &h->Ab[n], (size_t)s.I[n] * h->Jb[n]))) return bail(rc);
@@ -637,6 +656,13 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
     if (hipMemsetAsync(h->A[n], 0, (size_t)s.I[n] * s.Jp[n] * 4, h->stream) != hipSuccess) {
       h->last_error = "hipMemset failed";
       return bail(STD_E_DEVICE);
+    }
+    if (h->mu > 0) {
+      if ((rc = dalloc(h, &h->VA[n], (size_t)s.I[n] * s.Jp[n]))) return bail(rc);
+      if (hipMemsetAsync(h->VA[n], 0, (size_t)s.I[n] * s.Jp[n] * 4, h->stream) != hipSuccess) {
+        h->last_error = "hipMemset failed";
+        return bail(STD_E_DEVICE);
+      }
     }
   }
   if (hipMemsetAsync(h->xrow, 0xFF, (size_t)h->nb * N * stdk::xrow_stride(h->W) * 4, h->stream) != hipSuccess ||
@@ -888,7 +914,7 @@ bool batch_compatible(stdecomp_handle* const* hs, int n, size_t* lds) {
   for (int i = 0; i < n && ok; ++i) {
     const stdecomp_handle* h = hs[i];
     ok = h->device == h0->device && h->dtype == h0->dtype && h->threads == h0->threads && h->R == 0 &&
-         h->W == h0->W && (h->s.N == 3) == (h0->s.N == 3);
+         h->W == h0->W && (h->s.N == 3) == (h0->s.N == 3) && (h->mu > 0) == (h0->mu > 0);
     for (int k = 0; k < i && ok; ++k) ok = hs[k] != h;
     *lds = h->chain_lds > *lds ? h->chain_lds : *lds;
   }
@@ -999,7 +1025,7 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
     hipck(hipMemsetAsync(dflags, 0, flag_bytes, h0->stream), "memset");
     hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
           "batched launch arguments");
-    hipck(stdk::launch_chain_queue(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, dargs, dlist, nslots, W, h0->threads,
+    hipck(stdk::launch_chain_queue(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, h0->mu > 0, dargs, dlist, nslots, W, h0->threads,
                                    lds, h0->stream),
           "batched chain launch");
     hipck(hipStreamSynchronize(h0->stream), "batched chain launch");  // (args reused next)
@@ -1243,36 +1269,38 @@ int stdecomp_loss(stdecomp_handle* h, int64_t n, const int32_t* idx, const float
   return STD_OK;
 }
 
-int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G) {
-  if (!h) return STD_E_STATE;
+namespace {
+
+// Copy factor-shaped device arrays (padded rows, dA[n] I_n x Jp_n) and a
+// core-shaped one out to host arrays of I_n x J_n rows and P floats: one
+// contiguous copy per factor (a pitched copy from pageable memory goes row by
+// row), unpacked on the host.
+int copy_params_out(stdecomp_handle* h, float* const* dA, const float* dG, float* const* A, float* G) {
   if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
-  // one contiguous copy per factor (padded rows), unpacked on the host: a
-  // pitched copy from pageable memory goes row by row
   std::vector<float> buf;
   for (int n = 0; n < h->s.N; ++n) {
     if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
     const int J = h->s.J[n], Jp = h->s.Jp[n];
     const size_t rows = (size_t)h->s.I[n];
     if (J == Jp) {
-      HIPCHK(h, hipMemcpyAsync(A[n], h->A[n], rows * J * 4, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(A[n], dA[n], rows * J * 4, hipMemcpyDeviceToHost, h->stream));
       HIPCHK(h, hipStreamSynchronize(h->stream));
     } else {
       buf.resize(rows * Jp);
-      HIPCHK(h, hipMemcpyAsync(buf.data(), h->A[n], buf.size() * 4, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(buf.data(), dA[n], buf.size() * 4, hipMemcpyDeviceToHost, h->stream));
       HIPCHK(h, hipStreamSynchronize(h->stream));
       for (size_t i = 0; i < rows; ++i) std::memcpy(A[n] + i * J, buf.data() + i * Jp, (size_t)J * 4);
     }
   }
-  HIPCHK(h, hipMemcpyAsync(G, h->G, (size_t)h->s.P * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(G, dG, (size_t)h->s.P * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return STD_OK;
 }
 
-int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G) {
-  if (!h) return STD_E_STATE;
+// The reverse: packed on the host into the padded row layout (padding stays
+// zero) and sent in one contiguous copy per factor.
+int copy_params_in(stdecomp_handle* h, float* const* dA, float* dG, const float* const* A, const float* G) {
   if (!A || !G) return fail(h, STD_E_INVAL, "NULL parameter pointer");
-  // packed on the host into the padded row layout (padding stays zero) and
-  // sent in one contiguous copy per factor
   for (int n = 0; n < h->s.N; ++n)
     if (!A[n]) return fail(h, STD_E_INVAL, "NULL factor pointer");
   std::vector<float> buf;
@@ -1280,17 +1308,42 @@ int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* 
     const int J = h->s.J[n], Jp = h->s.Jp[n];
     const size_t rows = (size_t)h->s.I[n];
     if (J == Jp) {
-      HIPCHK(h, hipMemcpyAsync(h->A[n], A[n], rows * J * 4, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(dA[n], A[n], rows * J * 4, hipMemcpyHostToDevice, h->stream));
     } else {
       buf.assign(rows * Jp, 0.f);
       for (size_t i = 0; i < rows; ++i) std::memcpy(buf.data() + i * Jp, A[n] + i * J, (size_t)J * 4);
-      HIPCHK(h, hipMemcpyAsync(h->A[n], buf.data(), buf.size() * 4, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(dA[n], buf.data(), buf.size() * 4, hipMemcpyHostToDevice, h->stream));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));  // buf is reused for the next factor
   }
-  HIPCHK(h, hipMemcpyAsync(h->G, G, (size_t)h->s.P * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(dG, G, (size_t)h->s.P * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  return refresh_bf16(h);
+  return STD_OK;
+}
+
+}  // namespace
+
+int stdecomp_get_params(stdecomp_handle* h, float* const* A, float* G) {
+  if (!h) return STD_E_STATE;
+  return copy_params_out(h, h->A, h->G, A, G);
+}
+
+int stdecomp_set_params(stdecomp_handle* h, const float* const* A, const float* G) {
+  if (!h) return STD_E_STATE;
+  const int rc = copy_params_in(h, h->A, h->G, A, G);
+  return rc ? rc : refresh_bf16(h);
+}
+
+int stdecomp_get_velocity(stdecomp_handle* h, float* const* VA, float* VG) {
+  if (!h) return STD_E_STATE;
+  if (!h->VG) return fail(h, STD_E_STATE, "the handle has no momentum (options.momentum = 0)");
+  return copy_params_out(h, h->VA, h->VG, VA, VG);
+}
+
+int stdecomp_set_velocity(stdecomp_handle* h, const float* const* VA, const float* VG) {
+  if (!h) return STD_E_STATE;
+  if (!h->VG) return fail(h, STD_E_STATE, "the handle has no momentum (options.momentum = 0)");
+  return copy_params_in(h, h->VA, h->VG, VA, VG);
 }
 
 int stdecomp_get_kruskal(stdecomp_handle* h, float* const* B) {
