@@ -265,6 +265,12 @@ CASES = [
     ("n3_j10_w4_ragged", (300, 200, 100), (10, 10, 10), 9001, 1024, 256, 1.1),
     ("n3_j16", (100, 90, 80), (16, 16, 16), 6000, 256, 64, None),
     ("n3_j5_chunk1", (50, 40, 30), (5, 5, 5), 700, 8, 1, 1.5),
+    # the largest order (eight modes, the generic-order kernel with every mode loop at its bound)
+    ("n8_j2_w4", (9, 8, 7, 6, 6, 5, 5, 4), (2, 2, 2, 2, 2, 2, 2, 2), 2000, 64, 16, 1.2),
+    # an epoch shorter than one minibatch: a single ragged minibatch of 37 entries
+    ("n3_one_ragged_minibatch", (30, 20, 10), (3, 4, 2), 37, 64, 16, None),
+    # unequal ranks on four modes with the largest rank 16 (generic kernel, two-stage contraction)
+    ("n4_unequal_j16_w8", (40, 30, 20, 10), (16, 4, 2, 3), 6000, 256, 32, 1.1),
     # rank 20: the generic-rank kernel; at M = 4096 the automatic chunk (64, 64
     # workgroups) leaves 88 floats of the workgroup's LDS unused
     ("n3_j20_w4", (100, 90, 80), (20, 20, 20), 6000, 256, 64, None),
