@@ -405,16 +405,18 @@ def chain_roofline(acc, dtype, traffic, lat):
 def run_c4(args):
     """64 independent three-mode tensors (mode sizes 10^U(3,6), 10^U(4,7)
     entries, uniform indices, equal ranks from {4, 8, 16}, planted models plus
-    N(0, 0.01^2) noise); M = 1024, lr = lambda = 0.01, 128-entry chunks (8
-    workgroups per chain).  One batched call per epoch runs all 64 chains in
-    one cooperative launch: slots of 8 workgroups, as many as the device
-    holds, each running a list of chains balanced on the host (longest
-    first).  The comparison runs every model alone, one after another.
-    value = all models' nonzero-updates per second of batched epochs."""
+    N(0, 0.01^2) noise); M = 1024, lr = lambda = 0.01.  The chunk (and so the
+    workgroups per chain) is one for the whole batch: --chunk, or by default
+    the tuner's pick from timing one batched epoch with each candidate.  One
+    batched call per epoch runs all 64 chains in one cooperative launch:
+    slots of W workgroups, as many as the device holds, each running a list
+    of chains balanced on the host (longest first).  The comparison runs
+    every model alone, one after another.  value = all models'
+    nonzero-updates per second of batched epochs."""
     import numpy as np
     import torch
     from oracle import oracle
-    from paper_2012_03550_amd import binding, synth
+    from paper_2012_03550_amd import binding, synth, tune
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -422,9 +424,17 @@ def run_c4(args):
     wls = synth.planted_batch(n=64, device="cuda")
     total = sum(w.nnz for w in wls)
     log("generated %d tensors, %d entries in %.1fs" % (len(wls), total, time.time() - t))
-    M, lr, lam, chunk = 1024, 0.01, 0.01, 128
+    M, lr, lam = 1024, 0.01, 0.01
     res = {}
     for dtype in ("f32", "bf16"):
+        if args.chunk > 0:
+            chunk, rates = args.chunk, None
+        else:  # one chunk for the whole batch, by timing a batched epoch with each candidate
+            t = time.time()
+            chunk, rates = tune.tune_batch([(w.dims, w.ranks, w.train_idx, w.train_vals) for w in wls], M, dtype=dtype,
+                                           lr=lr, lam=lam)
+            log("c4 %s tuner (%.1fs): %s -> chunk %d" % (dtype, time.time() - t,
+                                                       {c: "%.3e" % r for c, r in rates.items()}, chunk))
         hs = [binding.Stdecomp(w.dims, w.ranks, w.train_idx, w.train_vals, batch=M, lr_factor=lr, lr_core=lr,
                                lam_factor=lam, lam_core=lam, seed_sample=3004 + k, seed_init=2004 + k, chunk=chunk,
                                dtype=dtype) for k, w in enumerate(wls)]
@@ -452,7 +462,9 @@ def run_c4(args):
             h.close()
         log("c4 %s: batched %.3e updates/s, one model at a time %.3e" % (dtype, batched, alone))
         Js = sorted({w.ranks[0] for w in wls})
-        res[dtype] = {"updates_per_s": round(batched, 1), "alone_updates_per_s": round(alone, 1),
+        res[dtype] = {"chunk": chunk, "workgroups_per_chain": -(-M // chunk),
+                      "tuner_updates_per_s": {str(c): round(r, 1) for c, r in rates.items()} if rates else None,
+                      "updates_per_s": round(batched, 1), "alone_updates_per_s": round(alone, 1),
                       "speedup": round(batched / alone, 3), "ms_per_step": round(wall / args.steps * 1e3, 3),
                       "ranks": {str(j): sum(1 for w in wls if w.ranks[0] == j) for j in Js},
                       "roofline": chain_roofline(acc, dtype, None, None),
@@ -475,7 +487,7 @@ def run_c4(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "64 planted three-mode tensors, mode sizes 10^U(3,6), 10^U(4,7) entries, J from "
                                   "{4,8,16}, M=1024, lr=lambda=0.01; step = 1 epoch of every tensor, one batched launch",
-                      "tensors": len(wls), "entries": int(total), "batch": M, "chunk": chunk},
+                      "tensors": len(wls), "entries": int(total), "batch": M, "chunk": res["f32"]["chunk"]},
            "roofline": res["f32"]["roofline"], "f32": res["f32"], "bf16": res["bf16"],
            "cpu_baseline": dict({"value": round(upd / dt, 1), "unit": "nonzero-updates/s", "cores": 1, "kind": "oracle",
                                  "sample": "one epoch of each of the 4 smallest tensors (%d updates), FP64 C, one "

@@ -633,6 +633,28 @@ def test_chunk_tuner(lib):
     h.close()
 
 
+def test_batch_tuner(lib):
+    """The batch tuner times one batched epoch of every model with each
+    candidate chunk (one chunk for all: the chains must share the workgroup
+    count) and returns the highest rate; the batch trains with it in one
+    launch; the decision is cached per set of shapes."""
+    from paper_2012_03550_amd import tune
+    models = []
+    for k, (dims, ranks, nnz) in enumerate([((200, 150, 100), (4, 4, 4), 20000), ((120, 90, 60), (8, 8, 8), 9000),
+                                            ((300, 40, 70), (5, 5, 5), 15000)]):
+        idx, vals = synth.random_tiny(3, dims, ranks, nnz, seed=80 + k, skew=1.2)
+        models.append((dims, ranks, idx, (vals * 0.5).astype(np.float32)))
+    best, rates = tune.tune_batch(models, 512, candidates=(32, 64, 128))
+    say("batch tuner", rates, "->", best)
+    assert set(rates) == {32, 64, 128} and best == max(rates, key=rates.get) and min(rates.values()) > 0
+    assert tune.tune_batch(models, 512, candidates=(32, 64, 128))[0] == best  # cached
+    hs = [lib.Stdecomp(d, r, i, v, batch=512, chunk=best) for d, r, i, v in models]
+    st = lib.epoch_batched(hs, 1)
+    assert len({s["chain_seconds"] for s in st}) == 1 and all(s["epochs_run"] == 1 for s in st)
+    for h in hs:
+        h.close()
+
+
 def test_barrier_probe(lib):
     """The grid-barrier timing aid returns a positive time and rejects bad
     arguments."""
