@@ -147,7 +147,7 @@ size_t plan_chain_lds(ChainArgs& a, int threads, bool bf, int* aux) {
                   al(a.W > 1 ? (size_t)a.W * a.carry_stride : 0) + al((size_t)hm_len) +
                   al((size_t)(threads / 64) * L.wstride) + 2 * (size_t)a.W + 8;
   const size_t all_resident = common + al(tbf(tb_sum)) + al((size_t)tb_sum);
-  L.tb_all = all_resident * 4 <= 163840 ? 1 : 0;
+  L.tb_all = all_resident * 4 <= (size_t)(a.lds_cap > 0 ? a.lds_cap : 163840) ? 1 : 0;
   size_t off = 0;
   L.gs = (int)off;    off += al(s.P);
   L.vg = (int)off;    off += al(vg_len);

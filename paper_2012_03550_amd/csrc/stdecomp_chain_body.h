@@ -785,6 +785,10 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
 #pragma unroll
               for (int t = 0; t < TT; ++t)
                 bv[t] = *reinterpret_cast<const s16x4*>(tb16 + ((min(ct0 + t * nwb, ctn - 1) * ks2 + ks) * 64 + lane) * 4);
+              // (all four loads in flight before the first MFMA: without this use
+              // the register allocator, at its bound, gives them one register pair
+              // and serialises them)
+              asm volatile("" ::"v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]));
 #pragma unroll
               for (int t = 0; t < TT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(avb[ks], bv[t], acc[t], 0, 0, 0);
             }
@@ -795,12 +799,14 @@ __device__ __forceinline__ void mfma_E(const Shape& s, const PhaseTab& g, const 
           const int ct = ct0 + t * nwb;
           const int h = ct * hpt + hh;
           if (colok && ct < ctn && h < khi) {
+            f32x4 hq[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const f32x4 hv = hpr.quad(prow + 8 * q, h);
+            for (int q = 0; q < 4; ++q) hq[q] = hpr.quad(prow + 8 * q, h);
+            asm volatile("" ::"v"(hq[0]), "v"(hq[1]), "v"(hq[2]), "v"(hq[3]));  // (the four reads in one batch)
 #pragma unroll
-              for (int i = 0; i < 4; ++i) S[4 * q + i] = fmaf(hv[i], acc[t][4 * q + i], S[4 * q + i]);
-            }
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) S[4 * q + i] = fmaf(hq[q][i], acc[t][4 * q + i], S[4 * q + i]);
           }
         }
       }
@@ -1156,10 +1162,13 @@ __device__ __forceinline__ void mfma_core_grad4(const PhaseTab& g, const float* 
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
       const int col = (cg0 + c) * 16 + r16;
+      const int r0 = rt * 16 + 4 * kq;  // this lane's four rows r0 .. r0 + 3 are adjacent in out
+      if constexpr (R % 4 == 0) {  // one 16-byte store (r0 and R multiples of four)
+        if (cg0 + c < T16 && r0 < R && col < R) *reinterpret_cast<f32x4*>(out + r0 + R * col) = acc[c];
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = rt * 16 + 4 * kq + i;
-        if (cg0 + c < T16 && r < R && col < R) out[r + R * col] = acc[c][i];
+        for (int i = 0; i < 4; ++i)
+          if (cg0 + c < T16 && r0 + i < R && col < R) out[r0 + i + R * col] = acc[c][i];
       }
     }
   }
@@ -1667,7 +1676,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
         const int l4 = w * L.cper + tid;
         if (tid < L.cper && l4 < P4) {
           f32x4 sum = {0.f, 0.f, 0.f, 0.f};
-          for (int g2 = 0; g2 < L.cgrp; ++g2) sum += red[g2 * L.cper + tid];
+          // the groups in order, eight loads in flight
+          for (int g0 = 0; g0 < L.cgrp; g0 += 8) {
+            f32x4 t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = red[min(g0 + u, L.cgrp - 1) * L.cper + tid];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (g0 + u < L.cgrp) sum += t[u];
+          }
           const float inv_m = 1.0f / (float)m;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -1687,13 +1704,18 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
         passed += 1;
         barrier_arrive(a, w, passed);
         if (!barrier_wait(a, passed, misc + 7)) return;
-        for (int l4b = tid; l4b < P4; l4b += BT) {
-          float gv[4];
+        // (all of a thread's loads issued before its first LDS store: one round trip)
+        for (int l0 = tid; l0 < P4; l0 += 4 * BT) {
+          float gv[4][4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) gv[e] = a.G[min(4 * l4b + e, P - 1)];
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (4 * l4b + e < P) Gs[4 * l4b + e] = gv[e];
+            for (int e = 0; e < 4; ++e) gv[u][e] = a.G[min(4 * (l0 + u * BT) + e, P - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (4 * (l0 + u * BT) + e < P) Gs[4 * (l0 + u * BT) + e] = gv[u][e];
         }
         __syncthreads();
         if (L.tb_all)  // mode 0's table now; the others after this phase's arrival

@@ -152,6 +152,8 @@ struct ChainArgs {
   unsigned passed0;         // barriers the flags in bar have counted before this chain starts
   int jv;                   // rank variant of the chain body (chain_variant of s)
   int split_cap;            // entries of the LDS split-row table
+  int lds_cap;              // LDS bytes a workgroup may use on the device (the plan keeps every
+                            // mode's table resident when all of it fits; 0: 160 KiB)
   ChainLayout lay;          // filled by plan_chain_lds
   PhaseTab pt[kMaxOrder + 1];
 };

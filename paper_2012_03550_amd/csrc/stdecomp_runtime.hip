@@ -31,6 +31,7 @@ struct stdecomp_handle {
   hipStream_t qstream = nullptr;  // predictions (may run while another thread trains the handle)
   int device = 0;
   int num_cus = 0;
+  int lds_cap = 0;  // LDS bytes per workgroup on the device (the chain plan's bound)
   // chain configuration
   int W = 1, chunk = 1, threads = 64, split_cap = 0, carry_stride = 0;
   size_t chain_lds = 0;
@@ -261,6 +262,8 @@ int configure_chain(stdecomp_handle* h, int chunk_req) {
     a.chunk = chunk;
     a.split_cap = h->split_cap;
     a.carry_stride = h->carry_stride;
+    a.lds_cap = (int)lds_cap;
+    h->lds_cap = (int)lds_cap;
     h->chain_lds = stdk::plan_chain_lds(a, h->threads, h->dtype == STD_DTYPE_BF16);
     if (h->chain_lds == 0) return fail(h, STD_E_INVAL, "inconsistent chain plan");
     // With the default chunk, halve it (more, smaller workgroups) until the
@@ -321,6 +324,7 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.W = h->W;
   a.chunk = h->chunk;
   a.carry_stride = h->carry_stride;
+  a.lds_cap = h->lds_cap;
   a.spin_limit = kSpinLimit;
   a.split_cap = h->split_cap;
   return a;
