@@ -84,7 +84,7 @@ def main():
                           "copy_GBs_read_plus_write": round(2 * n * 4 / sec / 1e9, 1)}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.config == "c3":
         run_c3(args)
