@@ -294,20 +294,23 @@ __device__ __forceinline__ void wave_segmented_scan(float (&u)[JR], int Jn, int 
 // finish_split_rows).  vrow: where the new velocity goes (momentum, the
 // storing workgroup), else null.
 template <int JR, bool EXACT, bool MOM>
-__device__ __forceinline__ void split_row_step(const ChainArgs& a, const float* cbuf, int cw, int pJ, const float* F,
-                                               bool add_b, float inv_c, float* ent, float* vrow) {
+__device__ __forceinline__ void load_split_ops(const ChainArgs& a, const float* cbuf, int cw, int pJ, float (&Fb)[JR],
+                                               float (&old)[JR], float (&vo)[JR]) {
   const int NS = 2 * a.W;
   const float* slotB = cbuf + cw * 2 + 1;
   const float* rowB = cbuf + (2 + pJ) * NS + cw;
-  // (every LDS read before the first write: the compiler cannot tell the
-  // table from the slots and would otherwise order each read after it)
-  float old[JR], Fb[JR], vo[JR];
 #pragma unroll
   for (int j = 0; j < JR; ++j) {
     Fb[j] = (EXACT || j < pJ) ? slotB[(2 + j) * NS] : 0.f;
     old[j] = (EXACT || j < pJ) ? rowB[j * a.W] : 0.f;
     vo[j] = (MOM && (EXACT || j < pJ)) ? rowB[(pJ + j) * a.W] : 0.f;
   }
+}
+
+template <int JR, bool EXACT, bool MOM>
+__device__ __forceinline__ void apply_split_step(const ChainArgs& a, int pJ, const float (&Fb)[JR], const float (&old)[JR],
+                                                 const float (&vo)[JR], const float* F, bool add_b, float inv_c,
+                                                 float* ent, float* vrow) {
 #pragma unroll
   for (int j = 0; j < JR; ++j) {
     if (EXACT || j < pJ) {
@@ -319,6 +322,16 @@ __device__ __forceinline__ void split_row_step(const ChainArgs& a, const float* 
       ent[4 + j] = old[j] - a.gA * st;
     }
   }
+}
+
+template <int JR, bool EXACT, bool MOM>
+__device__ __forceinline__ void split_row_step(const ChainArgs& a, const float* cbuf, int cw, int pJ, const float* F,
+                                               bool add_b, float inv_c, float* ent, float* vrow) {
+  // (every LDS read before the first write: the compiler cannot tell the
+  // table from the slots and would otherwise order each read after it)
+  float old[JR], Fb[JR], vo[JR];
+  load_split_ops<JR, EXACT, MOM>(a, cbuf, cw, pJ, Fb, old, vo);
+  apply_split_step<JR, EXACT, MOM>(a, pJ, Fb, old, vo, F, add_b, inv_c, ent, vrow);
 }
 
 // Finish the rows that straddled chunk boundaries in the previous factor
@@ -334,12 +347,13 @@ __device__ __forceinline__ void split_row_step(const ChainArgs& a, const float* 
 // at cbuf[(2 + pJ) 2W + (pJ + j) W + w] (a run that straddles took its old
 // row, and velocity, in the chunk where it began).  Fills the LDS table
 // `split` (row, the run's first boundary, then the new master row at +4) in
-// row order.  If `store`, also writes the rows (master, and BF16 copy in BF16
-// mode) and their velocities.
+// row order.  Workgroup st_w of st_n (st_n > 0) writes the rows of the
+// entries e with e mod st_n = st_w (master, and BF16 copy in BF16 mode) and
+// their velocities, so the stores are spread over the chain's workgroups.
 
 template <int JR, bool EXACT, bool BF, bool GROUPED, bool MOM>
 __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, const int* xr, const int* xn, int nsplit,
-                                  const float* cbuf, float* split, int sstride, bool store, int64_t kb) {
+                                  const float* cbuf, float* split, int sstride, int st_w, int st_n, int64_t kb) {
   const int tid = threadIdx.x, BT = blockDim.x;
   const int pJ = EXACT ? JR : a.s.J[pm];
   const int NS = 2 * a.W;
@@ -350,29 +364,40 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
     // where the run began and writes the entry
     if (tid < 64) {
       const int v = tid;
-      const int rowv = (v >= 1 && v < a.W) ? xr[v] : -1;
-      const int rowp = (v >= 2 && v - 1 < a.W) ? xr[v - 1] : -1;
-      const int rown = (v + 1 < a.W) ? xr[v + 1] : -1;
+      // every LDS read first, with clamped indices, so they are in flight
+      // together: the rows at the boundaries, this lane's before-slot, and
+      // the after-slot and entry number of the chunk where its run began
+      // (the run's start comes from the ballot, before the scans)
+      const int x0 = xr[min(v, a.W - 1)], xm = xr[min(max(v - 1, 0), a.W - 1)], xp = xr[min(v + 1, a.W - 1)];
+      const float* slotA = cbuf + min(v, a.W - 1) * 2;
+      const int ca = __float_as_int(slotA[NS]);
+      float u[JR], cc[1];
+#pragma unroll
+      for (int j = 0; j < JR; ++j) u[j] = (EXACT || j < pJ) ? slotA[(2 + j) * NS] : 0.f;
+      const int rowv = (v >= 1 && v < a.W) ? x0 : -1;
+      const int rowp = (v >= 2 && v - 1 < a.W) ? xm : -1;
+      const int rown = (v + 1 < a.W) ? xp : -1;
       const bool live = rowv >= 0;
       const bool first = live && rowp != rowv;
       const bool last = live && rown != rowv;
       const unsigned long long starts = __ballot(first);
       const unsigned long long upto = v == 63 ? ~0ull : ((2ull << v) - 1);
       const int ws = live ? 63 - __clzll(starts & upto) : v;  // first boundary of my run
-      const float* slotA = cbuf + min(v, a.W - 1) * 2;
-      float u[JR], cc[1];
-      cc[0] = live ? (float)__float_as_int(slotA[NS]) : 0.f;
+      const int wsc = min(max(ws, 1), a.W - 1);
+      const int e = xn[wsc];
+      const int cb = __float_as_int(cbuf[(wsc - 1) * 2 + 1 + NS]);
+      float Fb[JR], old[JR], vo[JR];
+      load_split_ops<JR, EXACT, MOM>(a, cbuf, wsc - 1, pJ, Fb, old, vo);
+      cc[0] = live ? (float)ca : 0.f;
 #pragma unroll
-      for (int j = 0; j < JR; ++j) u[j] = (live && (EXACT || j < pJ)) ? slotA[(2 + j) * NS] : 0.f;
+      for (int j = 0; j < JR; ++j) u[j] = live ? u[j] : 0.f;
       wave_segmented_scan<JR, EXACT>(u, pJ, v, ws);
       wave_segmented_scan<1, true>(cc, 1, v, ws);
       if (last) {
-        const int e = xn[ws];
-        const float* slotB = cbuf + (ws - 1) * 2 + 1;
-        const int c = (int)cc[0] + __float_as_int(slotB[NS]);
+        const int c = (int)cc[0] + cb;
         float* ent = split + e * sstride;
-        float* vrow = (MOM && store) ? a.VA[pm] + (int64_t)rowv * a.s.Jp[pm] : nullptr;
-        split_row_step<JR, EXACT, MOM>(a, cbuf, ws - 1, pJ, u, true, 1.0f / (float)c, ent, vrow);
+        float* vrow = (MOM && st_n > 0 && e % st_n == st_w) ? a.VA[pm] + (int64_t)rowv * a.s.Jp[pm] : nullptr;
+        apply_split_step<JR, EXACT, MOM>(a, pJ, Fb, old, vo, u, true, 1.0f / (float)c, ent, vrow);
         ent[0] = __int_as_float(rowv);
       }
     }
@@ -396,7 +421,7 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
           if (EXACT || j < pJ) F[j] += slotA[(2 + j) * NS];
       }
       float* ent = split + e * sstride;
-      float* vrow = (MOM && store) ? a.VA[pm] + (int64_t)row * a.s.Jp[pm] : nullptr;
+      float* vrow = (MOM && st_n > 0 && e % st_n == st_w) ? a.VA[pm] + (int64_t)row * a.s.Jp[pm] : nullptr;
       split_row_step<JR, EXACT, MOM>(a, cbuf, bw - 1, pJ, F, false, 1.0f / (float)c, ent, vrow);
       ent[0] = __int_as_float(row);
     }
@@ -447,16 +472,17 @@ __device__ __forceinline__ void finish_split_rows(const ChainArgs& a, int pm, co
         const float* slotB = cbuf + (bw - 1) * 2 + 1;
         const int cb = __float_as_int(slotB[NS]);
         float* ent = split + e * sstride;
-        float* vrow = (MOM && store) ? a.VA[pm] + (int64_t)row * a.s.Jp[pm] : nullptr;
+        float* vrow = (MOM && st_n > 0 && e % st_n == st_w) ? a.VA[pm] + (int64_t)row * a.s.Jp[pm] : nullptr;
         split_row_step<JR, EXACT, MOM>(a, cbuf, bw - 1, pJ, F, true, 1.0f / (float)(c + cb), ent, vrow);
         ent[0] = __int_as_float(row);
       }
     }
   }
   __syncthreads();
-  if (store) {
+  if (st_n > 0) {
     for (int e = tid; e < nsplit * pJ; e += BT) {
       const int en = e / pJ, j = e - en * pJ;
+      if (en % st_n != st_w) continue;
       const int row = __float_as_int(split[en * sstride]);
       const float v = split[en * sstride + 4 + j];
       a.A[pm][(int64_t)row * a.s.Jp[pm] + j] = v;
@@ -1473,11 +1499,10 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
 //   A row whose positions straddle chunk boundaries is finished at the start
 //   of the next sub-step from the chunks' carried partial sums and the
 //   carried old row (every workgroup computes it identically into an LDS
-//   table; workgroup 0 stores it; until the next barrier nobody else reads it
-//   from global memory, and the rows of that mode are read after the barrier
-//   that follows).
-// Carry slot elements: [0] row, [1] count, [2, 2+J) partial sum, [2+J, 2+2J)
-// old row; stored element-major (element e of slot sl at e * 2W + sl).
+//   table; workgroup w stores the entries e with e mod W = w; until the next
+//   barrier nobody else reads them from global memory, and the rows of that
+//   mode are read after the barrier that follows).
+// Carry layout: at finish_split_rows.
 // ---------------------------------------------------------------------------
 template <int JU, int NU, int BFI>
 __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
@@ -1766,8 +1791,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       // ---- 3. rows of the previous factor sub-step that straddled chunks
       if (splits) {
         const int nsplit = misc[0];
-        finish_split_rows<JR, EXACT, BF, NU != 3, MOM>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w == 0,
-                                                  ph == 0 ? b - 1 : b);
+        finish_split_rows<JR, EXACT, BF, NU != 3, MOM>(a, pm, xa, xn, nsplit, cbuf, split, sstride, w, a.W,
+                                                       ph == 0 ? b - 1 : b);
         // the schedule says which entry (if any) holds this sample's mode-pm row
         const int pe = (cur.meta >> kMetaPatchShift) & 0xFF;
         if (active && pe > 0) {
@@ -1995,7 +2020,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
     if (tid == 0) misc[0] = xsrc[2 * a.W];
     copy_carry(a, ppar, cbuf);
     __syncthreads();
-    finish_split_rows<JR, EXACT, BF, NU != 3, MOM>(a, pm, xa, xn, misc[0], cbuf, split, sstride, true, a.b_end - 1);
+    finish_split_rows<JR, EXACT, BF, NU != 3, MOM>(a, pm, xa, xn, misc[0], cbuf, split, sstride, 0, 1, a.b_end - 1);
   }
   if constexpr (MOM) {  // the core velocity: each workgroup its slice (two levels), else workgroup 0
     if (CORE2) {
