@@ -179,7 +179,7 @@ def run_c2(args):
         "config": {"workload": "ratings_zipf 480000x18000x2000 100M nnz (Zipf 1.1, ratings 1-5, 10% held out), "
                                "J=(10,10,10), M=4096, lr=lambda=0.01; step = 1 epoch + held-out RMSE",
                    "train_entries": int(wl.nnz), "batch": M, "chain_workgroups": info["workgroups"],
-                   "chain_chunk": info["chunk"]},
+                   "chain_chunk": info["chunk"], "chain_placement": PLACEMENT_NAMES[info["placement"]]},
         "heldout_rmse": round(ls["rmse"], 6),
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -241,7 +241,8 @@ def run_c3(args):
                 worker.start()
         info = h.info()
         log("c3 %s chain" % dtype, info)
-        r = {"chain_workgroups": info["workgroups"], "chain_chunk": info["chunk"]}
+        r = {"chain_workgroups": info["workgroups"], "chain_chunk": info["chunk"],
+             "chain_placement": PLACEMENT_NAMES[info["placement"]]}
         if prefix > 0:
             h.run_minibatches(0, 0, prefix)
             r["prefix_params"] = h.get_params() + ((h.get_kruskal(),) if R else ())
@@ -321,7 +322,7 @@ def run_c3(args):
                                       nnz, "; Kruskal core R=%d" % R if R else "",
                                       "; heavy-ball momentum mu=%g" % mu if mu > 0 else ""),
                       "train_entries": int(wl.nnz), "batch": M, "r_core": R, "momentum": mu, "chain_workgroups": head["chain_workgroups"],
-                      "chain_chunk": head["chain_chunk"]},
+                      "chain_chunk": head["chain_chunk"], "chain_placement": head["chain_placement"]},
            "heldout_rmse": head["heldout_rmse_per_step"][-1] if head["heldout_rmse_per_step"] else None,
            "roofline": head["roofline"], "precision": precision, "cpu_baseline": cpu}
     for dtype in dtypes[1:]:
@@ -676,6 +677,9 @@ def host_cpu():
     return {"host_cpu": model, "host_threads": os.cpu_count()}
 
 
+PLACEMENT_NAMES = {1: "spread", 2: "one_xcc"}
+
+
 def traffic_path(workload, dtype):
     return os.path.join(ROOT, "profiles", "chain_traffic_%s%s.json" % (workload, "" if dtype == "f32" else "_" + dtype))
 
@@ -684,12 +688,13 @@ def stored_traffic(path, dtype, train_entries, batch, info):
     """HBM bytes per chain launch (FETCH_SIZE and WRITE_SIZE scaled by the
     copy-kernel factors) from a stored counter record, if it was taken on this
     kernel source, dtype, training-set size, minibatch size and chain geometry
-    (workgroups, chunk); else None."""
+    (workgroups, chunk, placement); else None."""
     if not os.path.exists(path):
         return None
     tj = json.load(open(path))
     want = {"kernel_source_hash": kernel_source_hash(), "dtype": dtype, "train_entries": int(train_entries),
-            "batch": int(batch), "workgroups": int(info["workgroups"]), "chunk": int(info["chunk"])}
+            "batch": int(batch), "workgroups": int(info["workgroups"]), "chunk": int(info["chunk"]),
+            "placement": PLACEMENT_NAMES[info["placement"]]}
     if any(tj.get(k) != v for k, v in want.items()):
         return None
     return tj.get("bytes_per_launch")

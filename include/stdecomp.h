@@ -54,6 +54,16 @@ extern "C" {
 #define STD_INIT_PAPER 1  /* entries N(0.5, 0.1^2): the paper's experimental setting */
 #define STD_INIT_CALLER 2 /* zeros until stdecomp_set_params */
 
+/* Where the chain's workgroups run (options.placement).  A chain whose W
+ * workgroups fit the compute units of one XCC can run on one XCC: its grid
+ * barriers then order memory in that XCC's L2 instead of at device scope, and
+ * the values its workgroups exchange stay in L2.  Results are bit-identical
+ * either way. */
+#define STD_PLACE_AUTO 0    /* one XCC when W fits one and the dispatch was found to place
+                               block b on XCC b mod (XCC count), else spread */
+#define STD_PLACE_SPREAD 1  /* blocks 0..W-1, spread over the XCCs, device-scope barriers */
+#define STD_PLACE_ONE_XCC 2 /* one XCC, or STD_E_INVAL from stdecomp_init when it cannot */
+
 typedef struct stdecomp_handle stdecomp_handle;
 
 /* Caller-supplied device memory (e.g. a framework's caching allocator).
@@ -119,7 +129,10 @@ typedef struct {
                                   velocities of the size of the parameters (zero at init;
                                   stdecomp_get/set_velocity); the Kruskal core (r_core > 0)
                                   is refused (STD_E_INVAL) */
-  int32_t reserved[10];        /* must be zero */
+  int32_t placement;           /* STD_PLACE_*: the chain's workgroups on one XCC or spread
+                                  (stdecomp_step_batched / stdecomp_epoch_batched launches
+                                  always spread their chains) */
+  int32_t reserved[9];         /* must be zero */
 } stdecomp_options;
 
 typedef struct {
@@ -157,6 +170,7 @@ typedef struct {
   int64_t minibatches;     /* per epoch: ceil(T / M) */
   int64_t epoch;           /* next epoch index (the current one inside stdecomp_step_batched's windows) */
   int64_t cursor;          /* next minibatch of that epoch for stdecomp_step_batched (0 at an epoch start) */
+  int32_t placement;       /* STD_PLACE_ONE_XCC or STD_PLACE_SPREAD: where stdecomp_epoch runs the chain */
 } stdecomp_info_out;
 
 /* Fill *o with the defaults: M = 256, gamma = lambda = 0.01, seeds 0, scaled
@@ -282,6 +296,16 @@ int stdecomp_step_batched(stdecomp_handle* const* hs, int32_t n, int64_t max_min
  * chain cannot exceed m / ((N + 1) t_sync) updates/s.  STD_E_INVAL for a bad
  * reps or a null output, STD_E_DEVICE if a workgroup gave up waiting. */
 int stdecomp_debug_barrier(stdecomp_handle* h, int32_t reps, double* us_per_barrier);
+
+/* Self-test of the grid barrier's memory ordering in the handle's placement
+ * (STD_PLACE_*): `reps` rounds (1 <= reps <= 1000000) in which every chain
+ * workgroup writes the round number into its own word of a device buffer with
+ * a plain store, passes the barrier, reads all W words with plain loads and
+ * passes a second barrier.  *stale receives how many reads returned an older
+ * round (0 when the barrier orders memory as the chain needs).  STD_E_INVAL
+ * for a bad reps or a null output, STD_E_DEVICE if a workgroup gave up
+ * waiting. */
+int stdecomp_debug_barrier_check(stdecomp_handle* h, int32_t reps, int64_t* stale);
 
 /* The GPU sampler alone: out[q] = pi_e(q) for q in [0, T) (the epoch order of
  * Section "Stochastic Optimization", minibatch b = positions [bM, (b+1)M)).

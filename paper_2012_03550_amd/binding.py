@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libstdecomp.so")
 STD_OK, STD_E_INVAL, STD_E_NOMEM, STD_E_DEVICE, STD_E_STATE, STD_E_DIVERGED = 0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 0, "bf16": 1}
 INITS = {"scaled": 0, "paper": 1, "caller": 2}
+PLACEMENTS = {"auto": 0, "spread": 1, "one_xcc": 2}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -40,7 +41,7 @@ class Options(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("r_core", ctypes.c_int32), ("inputs_on_device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("chain_chunk", ctypes.c_int32), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p), ("report_train_rmse", ctypes.c_int32),
-                ("momentum", ctypes.c_float), ("reserved", ctypes.c_int32 * 10)]
+                ("momentum", ctypes.c_float), ("placement", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
 
 
 class EpochStats(ctypes.Structure):
@@ -58,7 +59,8 @@ class LossOut(ctypes.Structure):
 class InfoOut(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int32), ("chunk", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("lds_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("minibatches", ctypes.c_int64), ("epoch", ctypes.c_int64), ("cursor", ctypes.c_int64)]
+                ("minibatches", ctypes.c_int64), ("epoch", ctypes.c_int64), ("cursor", ctypes.c_int64),
+                ("placement", ctypes.c_int32)]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -86,6 +88,7 @@ SIGNATURES = {
                                              ctypes.c_int32, ctypes.c_void_p]),
     "stdecomp_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(InfoOut)]),
     "stdecomp_debug_barrier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "stdecomp_debug_barrier_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "stdecomp_epoch_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
                                               ctypes.POINTER(EpochStats)]),
     "stdecomp_step_batched": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int64,
@@ -205,12 +208,13 @@ class Stdecomp:
 
     def __init__(self, dims, ranks, idx, vals, batch=256, lr_factor=0.01, lr_core=0.01, lam_factor=0.01,
                  lam_core=0.01, seed_sample=0, seed_init=0, init="scaled", dtype="f32", chunk=0, stream=None,
-                 allocator=None, train_rmse=False, r_core=0, momentum=0.0):
+                 allocator=None, train_rmse=False, r_core=0, momentum=0.0, placement="auto"):
         """allocator: None (the library calls hipMalloc) or a TorchAllocator
         (every device buffer of the handle from torch's caching allocator);
         train_rmse: epoch() also reports the RMSE over the training set;
         r_core: 0 for a dense core, R > 0 for the Kruskal core of rank R;
-        momentum: heavy-ball factor mu in [0, 1) (0: the plain method)."""
+        momentum: heavy-ball factor mu in [0, 1) (0: the plain method);
+        placement: "auto", "spread" or "one_xcc" (where the chain's workgroups run)."""
         L = load()
         self.N = len(dims)
         self.dims = tuple(int(d) for d in dims)
@@ -242,6 +246,7 @@ class Stdecomp:
         opt.r_core = int(r_core)
         self.r_core = int(r_core)
         opt.momentum = float(momentum)
+        opt.placement = PLACEMENTS[placement]
         self.allocator = allocator  # kept alive as long as the handle: the library calls it
         if allocator is not None:
             opt.dev_alloc = allocator._alloc
@@ -401,6 +406,13 @@ class Stdecomp:
         us = ctypes.c_double(0.0)
         self._check(load().stdecomp_debug_barrier(self._h, reps, ctypes.byref(us)), "stdecomp_debug_barrier")
         return us.value
+
+    def barrier_check(self, reps=2000):
+        """Reads of another workgroup's word after a barrier that returned an
+        older round (0: the barrier orders memory as the chain needs)."""
+        n = ctypes.c_int64(-1)
+        self._check(load().stdecomp_debug_barrier_check(self._h, reps, ctypes.byref(n)), "stdecomp_debug_barrier_check")
+        return n.value
 
     def info(self):
         out = InfoOut()

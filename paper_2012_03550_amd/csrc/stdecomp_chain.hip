@@ -8,12 +8,15 @@ namespace stdk {
 
 // The chain's grid barrier alone, `reps` times in a row (no other work): the
 // sync cost t_sync that bounds a chain at m / ((N + 1) t_sync) updates/s.
+// (Placed as the chain is, so it times the chain's own barrier ordering.)
 __global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, int reps) {
   __shared__ int flag[1];
+  const int w = chain_workgroup(a);
+  if (w < 0) return;
   unsigned passed = 0;
   for (int r = 0; r < reps; ++r) {
     passed += 1;
-    barrier_arrive(a, blockIdx.x, passed);
+    barrier_arrive(a, w, passed);
     if (!barrier_wait(a, passed, flag)) return;
   }
 }
@@ -21,7 +24,50 @@ __global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, in
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st) {
   ChainArgs args = a;
   void* params[] = {&args, &reps};
-  return hipLaunchCooperativeKernel((const void*)k_barrier_probe, dim3(a.W), dim3(threads), params, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_barrier_probe, dim3(a.W * a.xs), dim3(threads), params, 0, st);
+}
+
+// The barrier's memory ordering, checked: before each of `reps` barriers
+// workgroup w writes the round number into its own line of `slots` (plain
+// store), and after it reads every workgroup's line (plain loads); a second
+// barrier keeps round r + 1's writes after every read of round r.  Each read
+// that does not return the current round adds one to *stale.
+__global__ __launch_bounds__(kChainThreads) void k_barrier_check(ChainArgs a, int reps, unsigned* slots,
+                                                                 unsigned long long* stale) {
+  __shared__ int flag[1];
+  const int w = chain_workgroup(a);
+  if (w < 0) return;
+  unsigned passed = 0;
+  unsigned long long bad = 0;
+  for (int r = 1; r <= reps; ++r) {
+    if (threadIdx.x == 0) slots[w * kFlagStride] = (unsigned)r;
+    passed += 1;
+    barrier_arrive(a, w, passed);
+    if (!barrier_wait(a, passed, flag)) return;
+    for (int v = threadIdx.x; v < a.W; v += blockDim.x) bad += slots[v * kFlagStride] != (unsigned)r ? 1 : 0;
+    passed += 1;
+    barrier_arrive(a, w, passed);
+    if (!barrier_wait(a, passed, flag)) return;
+  }
+  if (bad) atomicAdd(stale, bad);
+}
+
+hipError_t launch_barrier_check(const ChainArgs& a, int threads, int reps, unsigned* slots, unsigned long long* stale,
+                                hipStream_t st) {
+  ChainArgs args = a;
+  void* params[] = {&args, &reps, &slots, &stale};
+  return hipLaunchCooperativeKernel((const void*)k_barrier_check, dim3(a.W * a.xs), dim3(threads), params, 0, st);
+}
+
+// Where the dispatcher puts the blocks of a grid: out[b] = the XCC of block b.
+__global__ __launch_bounds__(64) void k_xcc_probe(int* out) {
+  const int x = xcc_id();
+  if (threadIdx.x == 0) out[blockIdx.x] = x;
+}
+
+hipError_t launch_xcc_probe(int* out, int blocks, hipStream_t st) {
+  k_xcc_probe<<<blocks, 64, 0, st>>>(out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

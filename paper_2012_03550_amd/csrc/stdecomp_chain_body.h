@@ -62,37 +62,57 @@ __device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_f
 
 // ---------------------------------------------------------------------------
 // Grid barrier: workgroup w publishes how many barriers it has reached in its
-// own flag word (bar[w * kFlagStride]); wave 0 of every workgroup polls all W
-// flags (one lane per flag) until each has reached the target.  No
-// read-modify-write on a shared word, so arrivals do not serialise.  Each
-// wave waits until its own global writes have completed, the workgroup
-// synchronises, and thread 0 publishes them all with one agent-scope release
-// store (one L2 write-back per workgroup instead of one per wave); on the
-// other side the polling wave acquires once and the workgroup barrier hands
-// that on to the other waves.  The wait has a give-up bound so a lost
-// workgroup can never hang the device (the error flag then stops every
-// workgroup).  Arrival and wait are separate calls so that work which reads
-// nothing the other workgroups write can run in between.
+// own flag word; wave 0 of every workgroup polls all W flags (one lane per
+// flag, device-scope loads, which miss the L1) until each has reached the
+// target.  No read-modify-write on a shared word, so arrivals do not
+// serialise.  Each wave waits until its own global writes have completed, the
+// workgroup synchronises, and thread 0 publishes them all with one flag
+// store; on the other side the polling wave acquires once at agent scope
+// (which invalidates the L1) and the workgroup barrier hands that on to the
+// other waves.  The wait has a give-up bound so a lost workgroup can never
+// hang the device (the error flag then stops every workgroup).  Arrival and
+// wait are separate calls so that work which reads nothing the other
+// workgroups write can run in between.
+//
+// Two releases.  Workgroups spread over the XCCs (a.xid < 0; flags kFlagStride
+// words apart) publish with an agent-scope release store, which first writes
+// this XCC's L2 back to memory so that the other XCCs can read what the
+// workgroup wrote.  When every workgroup runs on one XCC (a.xid >= 0; flags
+// packed, workgroup w's at bar[w]) they share one L2, where their writes meet:
+// a completed store (vmcnt) has reached it, as the L1 writes through, so the
+// flag is a plain store and nothing is written back; the chain's data then
+// stays in that L2 from one sub-step to the next.  (The acquire cannot be
+// narrowed to the L1 alone: `buffer_inv sc0` leaves stale L1 lines outside the
+// split-workgroup mode, which the barrier check, k_barrier_check, detects.)
 // ---------------------------------------------------------------------------
 // s_waitcnt operand (gfx9 encoding) that waits for vmcnt(0) only: vector memory
 // counter 0 (bits 3:0 and 15:14), export and LDS/scalar counters at their maxima.
 constexpr int kWaitVmcnt0 = 0x0F70;
+// On one XCC the flags are packed (workgroup w's at bar[w]) so that one wave's
+// poll of all W is one request, and the placement claim of chain_workgroup
+// sits in the last word of the flag buffer.
+__device__ __forceinline__ constexpr int kClaim(int W) { return W * kFlagStride - 1; }
 
 __device__ __forceinline__ void barrier_arrive(const ChainArgs& a, int w, unsigned passed) {
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(a.bar + w * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    if (a.xid >= 0)
+      __hip_atomic_store(a.bar + w, passed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_store(a.bar + w * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed, int* flag_lds) {
   if (threadIdx.x < 64) {
+    const int fs = a.xid >= 0 ? 1 : kFlagStride;  // flag stride: packed on one XCC
     long long spins = 0;
     int good = 1;
     for (;;) {
       bool ok = true;
       for (int v = threadIdx.x; v < a.W; v += 64)
-        ok = ok && __hip_atomic_load(a.bar + v * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= passed;
+        ok = ok && __hip_atomic_load(a.bar + v * fs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= passed;
       if (__all(ok)) break;
       if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         good = 0;
@@ -110,6 +130,38 @@ __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed
   }
   __syncthreads();
   return *flag_lds != 0;
+}
+
+// The XCC this wave runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return (int)(v & 15u);
+}
+
+// Workgroup index of this block in a chain placed by a.xs / a.xid, or -1 for a
+// block outside the chain.  Spread: blocks 0..W-1.  One XCC: the grid has W xs
+// blocks and the dispatcher deals them to the xs XCCs in turn (from an XCC
+// that changes from one dispatch to the next), so XCC xid receives the W
+// blocks of one residue b mod xs, and w = b / xs numbers them.  The first wave
+// to arrive claims its residue in bar[W kFlagStride - 1] (the last word of the flags, zero at
+// launch); a block on XCC xid with another residue would mean the dispatch
+// does not deal in turn: it sets the error flag to 2 and leaves, and the
+// chain stops at its next barrier.
+__device__ __forceinline__ int chain_workgroup(const ChainArgs& a) {
+  const int b = blockIdx.x;
+  if (a.xid < 0) return b;
+  if (xcc_id() != a.xid) return -1;
+  const unsigned r = (unsigned)(b % a.xs) + 1u;
+  int ok = 1;
+  if (__lane_id() == 0) {
+    unsigned e = 0;
+    ok = __hip_atomic_compare_exchange_strong(a.bar + kClaim(a.W), &e, r, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) || e == r;
+    if (!ok) __hip_atomic_store(a.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!__builtin_amdgcn_readfirstlane(ok)) return -1;
+  return b / a.xs;
 }
 
 // Record a non-finite parameter write (integer atomic; the plain load skips
@@ -2043,7 +2095,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
 
 template <int JU, int NU, int BFI>
 __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
-  chain_body<JU, NU, BFI>(a, blockIdx.x);
+  const int w = chain_workgroup(a);
+  if (w < 0) return;
+  chain_body<JU, NU, BFI>(a, w);
 }
 
 // Many independent chains in one cooperative launch (a batch of tensors):
@@ -2076,7 +2130,7 @@ hipError_t launch_chain_t(const ChainArgs& a, int threads, size_t bytes, hipStre
   hipError_t e = hipFuncSetAttribute((const void*)k_chain<JU, NU, BFI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e == hipSuccess)
-    e = hipLaunchCooperativeKernel((const void*)k_chain<JU, NU, BFI>, dim3(a.W), dim3(threads), params,
+    e = hipLaunchCooperativeKernel((const void*)k_chain<JU, NU, BFI>, dim3(a.W * a.xs), dim3(threads), params,
                                    (unsigned)bytes, st);
   return e;
 }

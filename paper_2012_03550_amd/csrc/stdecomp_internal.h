@@ -146,6 +146,11 @@ struct ChainArgs {
   int64_t b_begin, b_end;   // minibatches [b_begin, b_end) of the epoch
   float gA, lA, gG, lG;     // learning steps and L2 weights
   int W;                    // workgroups in the chain
+  int xs;                   // blocks per workgroup in the grid (W * xs blocks): 1 when spread, the
+                            // device's XCC count when on one XCC
+  int xid;                  // >= 0: the chain runs on the W blocks the dispatcher deals to XCC xid
+                            // (see chain_workgroup), and its grid barrier orders memory in that
+                            // XCC's L2; -1: blocks 0..W-1 spread over the XCCs, agent-scope barriers
   int chunk;                // samples per workgroup per phase (<= blockDim)
   int carry_stride;         // floats of carry per chunk: >= 4 + 3 J_max (4 + 4 J_max with momentum), x4
   long long spin_limit;     // barrier give-up bound (iterations)
@@ -178,6 +183,12 @@ hipError_t launch_debug_segments(const Shape& s, const uint32_t* coo_perm, const
 size_t plan_chain_lds(ChainArgs& a, int threads, bool bf16, int* aux = nullptr);
 hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st);
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st);
+// The barrier reps times with a data exchange around each (slots: W
+// kFlagStride words; stale: one counter, zero at launch).
+hipError_t launch_barrier_check(const ChainArgs& a, int threads, int reps, unsigned* slots, unsigned long long* stale,
+                                hipStream_t st);
+// XCC of every block of a grid of `blocks` blocks (out[b], blocks ints).
+hipError_t launch_xcc_probe(int* out, int blocks, hipStream_t st);
 // Many independent chains in one cooperative launch: slot q (workgroups
 // [q W, (q + 1) W)) runs the chains list[nslots + 1 + i], i in [list[q],
 // list[q + 1]), one after another, each from its own arguments dev_args[m]

@@ -32,6 +32,7 @@ struct stdecomp_handle {
   int device = 0;
   int num_cus = 0;
   int lds_cap = 0;  // LDS bytes per workgroup on the device (the chain plan's bound)
+  int xs = 1, xid = -1;  // chain placement (ChainArgs::xs / xid): one XCC when xid >= 0
   // chain configuration
   int W = 1, chunk = 1, threads = 64, split_cap = 0, carry_stride = 0;
   size_t chain_lds = 0;
@@ -129,6 +130,50 @@ struct ScratchTable {
 ScratchTable g_scratch;
 
 // Resolve the scratch array's address on the current device (once per device).
+const char* const kMisplaced =
+    "the dispatch did not deal the chain's blocks to the XCCs in turn, as the one-XCC placement needs "
+    "(create the handle with placement STD_PLACE_SPREAD)";
+
+// Placement of the chain (STD_PLACE_*).  One XCC needs W <= CUs per XCC and a
+// dispatch that deals the blocks to the X XCCs in turn (block b and block
+// b + X on the same XCC), which is checked here on a grid of W X blocks; the
+// chain then runs on the W blocks of a grid of W X that land on the XCC block 0
+// of this probe ran on (chain_workgroup).  A device with one XCC keeps blocks
+// 0..W-1 with the L2-ordered barrier.
+int choose_placement(stdecomp_handle* h, int req) {
+  h->xs = 1;
+  h->xid = -1;
+  if (req == STD_PLACE_SPREAD) return STD_OK;
+  int nx = 1;
+  if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, h->device) != hipSuccess || nx < 1) nx = 1;
+  const bool fits = h->num_cus % nx == 0 && h->W <= h->num_cus / nx;
+  int xid = -1;
+  if (fits) {
+    const int blocks = h->W * nx;
+    std::vector<int> ids((size_t)blocks, -1);
+    int* dids = reinterpret_cast<int*>(h->dscratch);  // (3 * 4096 doubles; blocks <= CUs)
+    if (stdk::launch_xcc_probe(dids, blocks, h->stream) != hipSuccess ||
+        hipMemcpyAsync(ids.data(), dids, (size_t)blocks * 4, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return fail(h, STD_E_DEVICE, "XCC placement probe failed");
+    bool rr = true;
+    for (int b = 0; b < blocks; ++b) rr = rr && ids[(size_t)b] == ids[(size_t)(b % nx)];
+    for (int x = 0; x < nx; ++x)
+      for (int y = 0; y < x; ++y) rr = rr && ids[(size_t)x] != ids[(size_t)y];
+    if (rr) xid = ids[0];
+  }
+  if (xid < 0) {
+    if (req == STD_PLACE_ONE_XCC)
+      return fail(h, STD_E_INVAL,
+                  fits ? "placement STD_PLACE_ONE_XCC: the dispatch does not place blocks round-robin over the XCCs"
+                       : "placement STD_PLACE_ONE_XCC: the chain has more workgroups than one XCC has compute units");
+    return STD_OK;
+  }
+  h->xs = nx;
+  h->xid = xid;
+  return STD_OK;
+}
+
 int resolve_scratch(stdecomp_handle* h) {
   std::lock_guard<std::mutex> lock(g_scratch.mu);
   if (h->device < 0 || h->device >= 64) return fail(h, STD_E_DEVICE, "device ordinal out of range");
@@ -322,6 +367,8 @@ stdk::ChainArgs chain_args(stdecomp_handle* h) {
   a.gG = h->gG;
   a.lG = h->lG;
   a.W = h->W;
+  a.xs = h->xs;
+  a.xid = h->xid;
   a.chunk = h->chunk;
   a.carry_stride = h->carry_stride;
   a.lds_cap = h->lds_cap;
@@ -539,8 +586,9 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
   if (o->init_kind < STD_INIT_SCALED || o->init_kind > STD_INIT_CALLER) return STD_E_INVAL;
   if (o->dtype != STD_DTYPE_F32 && o->dtype != STD_DTYPE_BF16) return STD_E_INVAL;
   if (o->r_core < 0 || o->r_core > 64) return STD_E_INVAL;
-  for (int i = 0; i < 10; ++i)
+  for (int i = 0; i < 9; ++i)
     if (o->reserved[i] != 0) return STD_E_INVAL;
+  if (o->placement < STD_PLACE_AUTO || o->placement > STD_PLACE_ONE_XCC) return STD_E_INVAL;
   if (!(o->momentum >= 0.f && o->momentum < 1.f)) return STD_E_INVAL;
   if (o->momentum > 0.f && o->r_core > 0) return STD_E_INVAL;
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr)) return STD_E_INVAL;
@@ -649,6 +697,7 @@ int stdecomp_init(const stdecomp_problem* p, const stdecomp_options* o, stdecomp
       (rc = dalloc(h, &h->flag, 1)) || (rc = dalloc(h, &h->qflag, 1)) ||
       (h->mu > 0 && (rc = dalloc(h, &h->VG, (size_t)P))))
     return bail(rc);
+  if ((rc = choose_placement(h, o->placement))) return bail(rc);
   if (h->mu > 0 && hipMemsetAsync(h->VG, 0, (size_t)P * 4, h->stream) != hipSuccess) {
     h->last_error = "hipMemset failed";
     return bail(STD_E_DEVICE);
@@ -853,6 +902,7 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
   nseg_host.resize((size_t)h->nb * N);
   HIPCHK(h, hipMemcpyAsync(nseg_host.data(), h->nseg, nseg_host.size() * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (err == 2) return fail(h, STD_E_DEVICE, kMisplaced);
   if (err) return fail(h, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
   if (nf != ~0ull) return diverged_at(h, epoch, nf);
   float t01 = 0, t12 = 0;
@@ -1018,6 +1068,8 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
         stdecomp_handle* h = hs[i];
         stdk::ChainArgs& a = args[i];
         a = chain_args(h);
+        a.xs = 1;  // (slots of W blocks each: spread placement)
+        a.xid = -1;
         a.b_begin = std::min(b0[i] + off, b1[i]);
         a.b_end = std::min(b0[i] + off + kBatchesPerLaunch, b1[i]);
         a.bar = dflags + (size_t)q * W * stdk::kFlagStride;
@@ -1407,10 +1459,37 @@ int stdecomp_debug_barrier(stdecomp_handle* h, int32_t reps, double* us_per_barr
   int err = 0;
   HIPCHK(h, hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (err == 2) return fail(h, STD_E_DEVICE, kMisplaced);
   if (err) return fail(h, STD_E_DEVICE, "barrier probe: a workgroup gave up waiting");
   float ms = 0.f;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   *us_per_barrier = 1000.0 * ms / reps;
+  return STD_OK;
+}
+
+int stdecomp_debug_barrier_check(stdecomp_handle* h, int32_t reps, int64_t* stale) {
+  if (!h) return STD_E_STATE;
+  if (reps < 1 || reps > 1000000 || !stale) return fail(h, STD_E_INVAL, "bad barrier check arguments");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, STD_E_DEVICE, "hipSetDevice failed");
+  stdk::ChainArgs a = chain_args(h);
+  // (the handle's loss scratch: W <= CUs lines of kFlagStride words, then the counter)
+  unsigned* slots = reinterpret_cast<unsigned*>(h->dscratch);
+  const size_t slot_words = (size_t)h->W * stdk::kFlagStride;
+  if ((slot_words + 2) * 4 > 3 * 4096 * sizeof(double)) return fail(h, STD_E_INVAL, "too many workgroups");
+  unsigned long long* dstale = reinterpret_cast<unsigned long long*>(h->dscratch + (slot_words + 1) / 2);
+  HIPCHK(h, hipMemsetAsync(h->err, 0, sizeof(int), h->stream));
+  HIPCHK(h, hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h->stream));
+  HIPCHK(h, hipMemsetAsync(slots, 0, slot_words * 4, h->stream));
+  HIPCHK(h, hipMemsetAsync(dstale, 0, sizeof(unsigned long long), h->stream));
+  HIPCHK(h, stdk::launch_barrier_check(a, h->threads, reps, slots, dstale, h->stream));
+  int err = 0;
+  unsigned long long n = 0;
+  HIPCHK(h, hipMemcpyAsync(&err, h->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&n, dstale, sizeof(n), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (err == 2) return fail(h, STD_E_DEVICE, kMisplaced);
+  if (err) return fail(h, STD_E_DEVICE, "barrier check: a workgroup gave up waiting");
+  *stale = (int64_t)n;
   return STD_OK;
 }
 
@@ -1489,6 +1568,7 @@ int stdecomp_info(const stdecomp_handle* h, stdecomp_info_out* out) {
   out->minibatches = h->nb;
   out->epoch = h->epoch;
   out->cursor = h->cursor;
+  out->placement = h->xid >= 0 ? STD_PLACE_ONE_XCC : STD_PLACE_SPREAD;
   return STD_OK;
 }
 

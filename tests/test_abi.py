@@ -76,3 +76,25 @@ def test_null_arguments_are_rejected_without_gpu():
     assert L.stdecomp_init(None, None, None) == binding.STD_E_INVAL
     assert L.stdecomp_free(None) == binding.STD_OK
     assert L.stdecomp_epoch(None, 1, None) == binding.STD_E_STATE
+
+
+def test_bad_placement_is_rejected_without_gpu():
+    """options.placement outside STD_PLACE_AUTO..STD_PLACE_ONE_XCC is refused
+    before any device call."""
+    import numpy as np
+    from paper_2012_03550_amd import binding
+    L = binding.load()
+    dims = np.array([4, 5, 6], np.int64)
+    ranks = np.array([2, 2, 2], np.int32)
+    idx = np.zeros((3, 8), np.int32)
+    vals = np.ones(8, np.float32)
+    p = binding.Problem(3, dims.ctypes.data_as(binding._i64p), ranks.ctypes.data_as(binding._i32p), 8,
+                        ctypes.c_void_p(idx.ctypes.data), ctypes.c_void_p(vals.ctypes.data))
+    for bad in (-1, 3):
+        o = binding.Options()
+        assert L.stdecomp_default_options(ctypes.byref(o)) == binding.STD_OK
+        assert o.placement == 0  # STD_PLACE_AUTO by default
+        o.placement = bad
+        h = ctypes.c_void_p()
+        assert L.stdecomp_init(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)) == binding.STD_E_INVAL
+        assert not h.value
