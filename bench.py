@@ -44,7 +44,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--nnz", type=int, default=0, help="entries before the held-out split (0: the config's)")
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0, help="chain chunk (c2, c3, c4; 0: automatic, c4: tuned)")
+    ap.add_argument("--placement", default="auto", choices=["auto", "spread", "one_xcc"],
+                    help="(c2, c3) where the chain's workgroups run (auto: one XCC when W fits one)")
     ap.add_argument("--cpu-batches", type=int, default=-1,
                     help="minibatches of the CPU oracle baseline (0: skip; -1: the config's default, c3: 48, c2: 60)")
     ap.add_argument("--prefix", type=int, default=200,
@@ -121,7 +123,7 @@ def run_c2(args):
     lr = lam = 0.01
     h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
                          lam_factor=lam, lam_core=lam, seed_sample=3002, seed_init=2002, dtype=args.dtype,
-                         chunk=args.chunk)
+                         chunk=args.chunk, placement=args.placement)
     info = h.info()
     log("chain", info)
     A0, G0 = h.get_params()
@@ -230,7 +232,7 @@ def run_c3(args):
     for dtype in dtypes:
         h = binding.Stdecomp(wl.dims, wl.ranks, wl.train_idx, wl.train_vals, batch=M, lr_factor=lr, lr_core=lr,
                              lam_factor=lam, lam_core=lam, seed_sample=seed_s, seed_init=seed_i, dtype=dtype,
-                             r_core=R, momentum=mu)
+                             r_core=R, momentum=mu, chunk=args.chunk, placement=args.placement)
         if A0 is None:
             A0, G0 = h.get_params()
             B0 = h.get_kruskal() if R else None
@@ -703,7 +705,7 @@ def stored_traffic(path, dtype, train_entries, batch, info):
 def kernel_source_hash():
     import hashlib
     hsh = hashlib.sha256()
-    for f in ("stdecomp_chain_body.h", "stdecomp_chain.hip", "stdecomp_device.h", "stdecomp_internal.h"):
+    for f in ("stdecomp_chain_body.h", "stdecomp_chain.hip", "stdecomp_chain_xcc.hip", "stdecomp_device.h", "stdecomp_internal.h"):
         hsh.update(open(os.path.join(ROOT, "paper_2012_03550_amd", "csrc", f), "rb").read())
     return hsh.hexdigest()[:16]
 

@@ -59,10 +59,12 @@ extern "C" {
  * barriers then order memory in that XCC's L2 instead of at device scope, and
  * the values its workgroups exchange stay in L2.  Results are bit-identical
  * either way. */
-#define STD_PLACE_AUTO 0    /* one XCC when W fits one and the dispatch was found to place
-                               block b on XCC b mod (XCC count), else spread */
+#define STD_PLACE_AUTO 0    /* one XCC when W fits one, the core is dense without momentum
+                               and the dispatch was found to deal blocks to the XCCs in
+                               turn, else spread */
 #define STD_PLACE_SPREAD 1  /* blocks 0..W-1, spread over the XCCs, device-scope barriers */
-#define STD_PLACE_ONE_XCC 2 /* one XCC, or STD_E_INVAL from stdecomp_init when it cannot */
+#define STD_PLACE_ONE_XCC 2 /* one XCC, or STD_E_INVAL from stdecomp_init when it cannot
+                               (also with r_core > 0 or momentum > 0) */
 
 typedef struct stdecomp_handle stdecomp_handle;
 

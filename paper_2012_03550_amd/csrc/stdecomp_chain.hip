@@ -9,22 +9,24 @@ namespace stdk {
 // The chain's grid barrier alone, `reps` times in a row (no other work): the
 // sync cost t_sync that bounds a chain at m / ((N + 1) t_sync) updates/s.
 // (Placed as the chain is, so it times the chain's own barrier ordering.)
+template <bool XL>
 __global__ __launch_bounds__(kChainThreads) void k_barrier_probe(ChainArgs a, int reps) {
   __shared__ int flag[1];
-  const int w = chain_workgroup(a);
+  const int w = chain_workgroup<XL>(a);
   if (w < 0) return;
   unsigned passed = 0;
   for (int r = 0; r < reps; ++r) {
     passed += 1;
-    barrier_arrive(a, w, passed);
-    if (!barrier_wait(a, passed, flag)) return;
+    barrier_arrive<XL>(a, w, passed);
+    if (!barrier_wait<XL>(a, passed, flag)) return;
   }
 }
 
 hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipStream_t st) {
   ChainArgs args = a;
   void* params[] = {&args, &reps};
-  return hipLaunchCooperativeKernel((const void*)k_barrier_probe, dim3(a.W * a.xs), dim3(threads), params, 0, st);
+  const void* k = a.xid >= 0 ? (const void*)k_barrier_probe<true> : (const void*)k_barrier_probe<false>;
+  return hipLaunchCooperativeKernel(k, dim3(a.W * a.xs), dim3(threads), params, 0, st);
 }
 
 // The barrier's memory ordering, checked: before each of `reps` barriers
@@ -32,22 +34,23 @@ hipError_t launch_barrier_probe(const ChainArgs& a, int threads, int reps, hipSt
 // store), and after it reads every workgroup's line (plain loads); a second
 // barrier keeps round r + 1's writes after every read of round r.  Each read
 // that does not return the current round adds one to *stale.
+template <bool XL>
 __global__ __launch_bounds__(kChainThreads) void k_barrier_check(ChainArgs a, int reps, unsigned* slots,
                                                                  unsigned long long* stale) {
   __shared__ int flag[1];
-  const int w = chain_workgroup(a);
+  const int w = chain_workgroup<XL>(a);
   if (w < 0) return;
   unsigned passed = 0;
   unsigned long long bad = 0;
   for (int r = 1; r <= reps; ++r) {
     if (threadIdx.x == 0) slots[w * kFlagStride] = (unsigned)r;
     passed += 1;
-    barrier_arrive(a, w, passed);
-    if (!barrier_wait(a, passed, flag)) return;
+    barrier_arrive<XL>(a, w, passed);
+    if (!barrier_wait<XL>(a, passed, flag)) return;
     for (int v = threadIdx.x; v < a.W; v += blockDim.x) bad += slots[v * kFlagStride] != (unsigned)r ? 1 : 0;
     passed += 1;
-    barrier_arrive(a, w, passed);
-    if (!barrier_wait(a, passed, flag)) return;
+    barrier_arrive<XL>(a, w, passed);
+    if (!barrier_wait<XL>(a, passed, flag)) return;
   }
   if (bad) atomicAdd(stale, bad);
 }
@@ -56,7 +59,8 @@ hipError_t launch_barrier_check(const ChainArgs& a, int threads, int reps, unsig
                                 hipStream_t st) {
   ChainArgs args = a;
   void* params[] = {&args, &reps, &slots, &stale};
-  return hipLaunchCooperativeKernel((const void*)k_barrier_check, dim3(a.W * a.xs), dim3(threads), params, 0, st);
+  const void* k = a.xid >= 0 ? (const void*)k_barrier_check<true> : (const void*)k_barrier_check<false>;
+  return hipLaunchCooperativeKernel(k, dim3(a.W * a.xs), dim3(threads), params, 0, st);
 }
 
 // Where the dispatcher puts the blocks of a grid: out[b] = the XCC of block b.
@@ -350,6 +354,10 @@ hipError_t launch_chain(const ChainArgs& a, int threads, hipStream_t st) {
       for (int n = 0; n < a.s.N; ++n)
         if (!a.VA[n]) return hipErrorInvalidValue;
     }
+  }
+  if (a.xid >= 0) {  // one XCC: the plain dense-core kernels only
+    if (a.mom || a.R > 0) return hipErrorInvalidValue;
+    return launch_chain_xcc(a, threads, bytes, st);
   }
   if (a.mom) return launch_chain_mom(a, threads, bytes, st);
   if (a.R > 0) {  // Kruskal core: kernels for equal ranks 5, 8, 10, else the generic-rank ones

@@ -93,20 +93,24 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // sits in the last word of the flag buffer.
 __device__ __forceinline__ constexpr int kClaim(int W) { return W * kFlagStride - 1; }
 
+// XL: the one-XCC form (a compile-time choice, so that the spread kernels
+// carry no trace of it).
+template <bool XL>
 __device__ __forceinline__ void barrier_arrive(const ChainArgs& a, int w, unsigned passed) {
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (a.xid >= 0)
+    if constexpr (XL)
       __hip_atomic_store(a.bar + w, passed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
       __hip_atomic_store(a.bar + w * kFlagStride, passed, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
+template <bool XL>
 __device__ __forceinline__ bool barrier_wait(const ChainArgs& a, unsigned passed, int* flag_lds) {
   if (threadIdx.x < 64) {
-    const int fs = a.xid >= 0 ? 1 : kFlagStride;  // flag stride: packed on one XCC
+    constexpr int fs = XL ? 1 : kFlagStride;  // flag stride: packed on one XCC
     long long spins = 0;
     int good = 1;
     for (;;) {
@@ -148,9 +152,10 @@ __device__ __forceinline__ int xcc_id() {
 // launch); a block on XCC xid with another residue would mean the dispatch
 // does not deal in turn: it sets the error flag to 2 and leaves, and the
 // chain stops at its next barrier.
+template <bool XL>
 __device__ __forceinline__ int chain_workgroup(const ChainArgs& a) {
   const int b = blockIdx.x;
-  if (a.xid < 0) return b;
+  if constexpr (!XL) return b;
   if (xcc_id() != a.xid) return -1;
   const unsigned r = (unsigned)(b % a.xs) + 1u;
   int ok = 1;
@@ -1401,8 +1406,8 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
       }
     }
     passed += 1;
-    barrier_arrive(a, w, passed);
-    if (!barrier_wait(a, passed, flag_lds)) return false;
+    barrier_arrive<false>(a, w, passed);
+    if (!barrier_wait<false>(a, passed, flag_lds)) return false;
     // 3. this workgroup's slice of the sum over workgroups (groups of threads
     //    add runs of workgroups in order, eight loads in flight, then the
     //    groups are added in order)
@@ -1450,8 +1455,8 @@ __device__ bool kruskal_core_step(const ChainArgs& a, int w, int64_t b, int m, i
       }
     }
     passed += 1;
-    barrier_arrive(a, w, passed);
-    if (!barrier_wait(a, passed, flag_lds)) return false;
+    barrier_arrive<false>(a, w, passed);
+    if (!barrier_wait<false>(a, passed, flag_lds)) return false;
     // 4. the summed matrix (every workgroup): the packed triangle into the
     //    [W | x] region, which the Gram is done with (coalesced, eight loads in
     //    flight), then unpacked within LDS
@@ -1564,6 +1569,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
   constexpr bool BF = (BFI & 1) != 0;
   constexpr bool KR = (BFI & 2) != 0;  // Kruskal core (a.R > 0)
   constexpr bool MOM = (BFI & 4) != 0;  // heavy-ball momentum (a.mom; never with the Kruskal core)
+  constexpr bool XL = (BFI & 8) != 0;   // one-XCC barrier (a.xid >= 0; dense core, no momentum)
   constexpr bool TS = NU != 3;  // two-stage contraction (layout of the tables)
   extern __shared__ float lds[];
   const Shape& s = a.s;
@@ -1779,8 +1785,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
           }
         }
         passed += 1;
-        barrier_arrive(a, w, passed);
-        if (!barrier_wait(a, passed, misc + 7)) return;
+        barrier_arrive<XL>(a, w, passed);
+        if (!barrier_wait<XL>(a, passed, misc + 7)) return;
         // (all of a thread's loads issued before its first LDS store: one round trip)
         for (int l0 = tid; l0 < P4; l0 += 4 * BT) {
           float gv[4][4];
@@ -2029,7 +2035,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
       //      the resident tables the core update changed, or, with one table
       //      region, the next phase's table.
       passed += 1;
-      barrier_arrive(a, w, passed);
+      barrier_arrive<XL>(a, w, passed);
       if (ph == 1 && L.tb_all) {
         for (int n2 = 1; n2 < N; ++n2) {
           const PhaseTab& q = a.pt[n2 + 1];
@@ -2050,7 +2056,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
         if (b2 < a.b_end) load_lane_rec<NM>(a, w, N, b2, ph2, nx2);
         else nx2.valid = false;
       }
-      if (!barrier_wait(a, passed, misc + 7)) return;
+      if (!barrier_wait<XL>(a, passed, misc + 7)) return;
       first = false;
       bsel ^= 1;
       cur = nx;
@@ -2095,7 +2101,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, const int w) {
 
 template <int JU, int NU, int BFI>
 __global__ __launch_bounds__(kChainThreads) void k_chain(ChainArgs a) {
-  const int w = chain_workgroup(a);
+  const int w = chain_workgroup<(BFI & 8) != 0>(a);
   if (w < 0) return;
   chain_body<JU, NU, BFI>(a, w);
 }

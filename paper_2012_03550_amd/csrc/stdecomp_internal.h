@@ -146,11 +146,6 @@ struct ChainArgs {
   int64_t b_begin, b_end;   // minibatches [b_begin, b_end) of the epoch
   float gA, lA, gG, lG;     // learning steps and L2 weights
   int W;                    // workgroups in the chain
-  int xs;                   // blocks per workgroup in the grid (W * xs blocks): 1 when spread, the
-                            // device's XCC count when on one XCC
-  int xid;                  // >= 0: the chain runs on the W blocks the dispatcher deals to XCC xid
-                            // (see chain_workgroup), and its grid barrier orders memory in that
-                            // XCC's L2; -1: blocks 0..W-1 spread over the XCCs, agent-scope barriers
   int chunk;                // samples per workgroup per phase (<= blockDim)
   int carry_stride;         // floats of carry per chunk: >= 4 + 3 J_max (4 + 4 J_max with momentum), x4
   long long spin_limit;     // barrier give-up bound (iterations)
@@ -161,6 +156,12 @@ struct ChainArgs {
                             // mode's table resident when all of it fits; 0: 160 KiB)
   ChainLayout lay;          // filled by plan_chain_lds
   PhaseTab pt[kMaxOrder + 1];
+  // (placement last, so that the fields above keep their kernel-argument offsets)
+  int xs;                   // blocks per workgroup in the grid (W * xs blocks): 1 when spread, the
+                            // device's XCC count when on one XCC
+  int xid;                  // >= 0: the chain runs on the W blocks the dispatcher deals to XCC xid
+                            // (see chain_workgroup), and its grid barrier orders memory in that
+                            // XCC's L2; -1: blocks 0..W-1 spread over the XCCs, agent-scope barriers
 };
 
 // Which J specialisation of the chain serves a shape: the common rank when
@@ -203,6 +204,9 @@ hipError_t launch_chain_queue(int n3, int bf, int mom, const ChainArgs* dev_args
 // The chain kernels with heavy-ball momentum (stdecomp_chain_mom.hip): one
 // chain (a.mom, dense core, plan already checked) and a batch of chains.
 hipError_t launch_chain_mom(const ChainArgs& a, int threads, size_t bytes, hipStream_t st);
+// The dense-core chain kernels without momentum with the one-XCC barrier
+// (stdecomp_chain_xcc.hip; a.xid >= 0, plan already checked).
+hipError_t launch_chain_xcc(const ChainArgs& a, int threads, size_t bytes, hipStream_t st);
 hipError_t launch_chain_queue_mom(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
                                   int threads, size_t bytes, hipStream_t st);
 hipError_t launch_pack_records(const Shape& s, const int32_t* idx, const float* vals, int64_t n,

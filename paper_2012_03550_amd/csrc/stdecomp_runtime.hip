@@ -144,6 +144,11 @@ int choose_placement(stdecomp_handle* h, int req) {
   h->xs = 1;
   h->xid = -1;
   if (req == STD_PLACE_SPREAD) return STD_OK;
+  if (h->R > 0 || h->mu > 0) {  // (one-XCC kernels exist for the dense core without momentum)
+    if (req == STD_PLACE_ONE_XCC)
+      return fail(h, STD_E_INVAL, "placement STD_PLACE_ONE_XCC: not available with the Kruskal core or momentum");
+    return STD_OK;
+  }
   int nx = 1;
   if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, h->device) != hipSuccess || nx < 1) nx = 1;
   const bool fits = h->num_cus % nx == 0 && h->W <= h->num_cus / nx;

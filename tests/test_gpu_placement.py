@@ -49,6 +49,19 @@ def test_auto_places_a_narrow_chain_on_one_xcc(lib):
         assert h.info()["placement"] == SPREAD
 
 
+def test_one_xcc_only_for_the_plain_dense_core(lib):
+    """The one-XCC kernels are those of the dense core without momentum: the
+    Kruskal core and momentum run spread (auto) or are refused (one XCC)."""
+    dims, ranks = (200, 150, 90), (5, 5, 5)
+    idx, vals = synth.random_tiny(3, dims, ranks, 15000, seed=6)
+    for extra in ({"momentum": 0.5}, {"r_core": 3}):
+        with lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, **extra) as h:
+            assert h.info()["placement"] == SPREAD
+        with pytest.raises(lib.StdecompError) as ei:
+            lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, placement="one_xcc", **extra)
+        assert ei.value.code == lib.STD_E_INVAL
+
+
 @pytest.mark.parametrize("W", [2, 16, 32])
 def test_barrier_orders_memory_in_both_placements(lib, W):
     dims, ranks = (300, 200, 100), (4, 4, 4)
@@ -69,8 +82,7 @@ CASES = [
     ("n4_j8_two_level_w16", (60, 50, 30, 20), (8, 8, 8, 8), 12000, 1024, 64, "f32", {}),
     ("n4_j4_bf16_w32", (80, 60, 40, 30), (4, 4, 4, 4), 20000, 2048, 64, "bf16", {}),
     ("n3_mixed_generic_w4", (60, 50, 40), (2, 3, 4), 3000, 32, 8, "f32", {}),
-    ("n3_j6_momentum_w16", (200, 150, 90), (6, 6, 6), 15000, 512, 32, "f32", {"momentum": 0.5}),
-    ("n3_j5_kruskal_w8", (200, 150, 90), (5, 5, 5), 15000, 512, 64, "f32", {"r_core": 3}),
+    ("n3_mixed_generic_bf16_w16", (300, 200, 100), (6, 4, 5), 12000, 1024, 64, "bf16", {}),
 ]
 
 
@@ -89,11 +101,6 @@ def test_placements_give_identical_bits(lib, case):
             h.epoch(2)
             A, G = h.get_params()
             res = [a.copy() for a in A] + [G.copy()]
-            if extra.get("momentum"):
-                VA, VG = h.get_velocity()
-                res += [v.copy() for v in VA] + [VG.copy()]
-            if extra.get("r_core"):
-                res += [b.copy() for b in h.get_kruskal()]
             out[place] = res
     for a, b in zip(out["one_xcc"], out["spread"]):
         assert np.all(np.isfinite(a))
