@@ -132,8 +132,9 @@ typedef struct {
                                   stdecomp_get/set_velocity); the Kruskal core (r_core > 0)
                                   is refused (STD_E_INVAL) */
   int32_t placement;           /* STD_PLACE_*: the chain's workgroups on one XCC or spread
-                                  (stdecomp_step_batched / stdecomp_epoch_batched launches
-                                  always spread their chains) */
+                                  (stdecomp_step_batched / stdecomp_epoch_batched put every
+                                  slot on one XCC when every handle of the batch is on one,
+                                  else spread them) */
   int32_t reserved[9];         /* must be zero */
 } stdecomp_options;
 

@@ -988,12 +988,37 @@ bool batch_compatible(stdecomp_handle* const* hs, int n, size_t* lds) {
 // the chain's latency-bound minibatch), and a slot runs its chains one after
 // another.  acc[i] receives the work and the launches' time (the whole
 // batched launch for every model).  Errors are reported on hs[0].
+}  // namespace
+
+namespace stdk {
+// Batched chains with every slot on one XCC (stdecomp_chain_queue_xcc.hip).
+hipError_t launch_chain_queue_xcc(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
+                                  int nx, int threads, size_t bytes, hipStream_t st);
+}  // namespace stdk
+
+namespace {
+
 int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std::vector<int64_t>& b0,
                        const std::vector<int64_t>& b1, std::vector<stdecomp_epoch_stats>& acc) {
   stdecomp_handle* h0 = hs[0];
   const int W = h0->W;
   if (hipSetDevice(h0->device) != hipSuccess) return fail(h0, STD_E_DEVICE, "hipSetDevice failed");
-  const int nslots = std::min(n, h0->num_cus / W);
+  int nslots = std::min(n, h0->num_cus / W);
+  // every slot on one XCC when every handle is placed on one (dense core, no
+  // momentum, W <= CUs per XCC): nslots a multiple of the XCC count nx, the
+  // slots of one XCC filling at most its CUs
+  const int nx = h0->xs;
+  bool local = true;
+  for (int i = 0; i < n && local; ++i) local = hs[i]->xid >= 0 && hs[i]->xs == nx;
+  if (local) {
+    const int cap = h0->num_cus / W;
+    int up = (nslots + nx - 1) / nx * nx;
+    if (up > cap) up = cap / nx * nx;
+    if (up < nx)
+      local = false;
+    else
+      nslots = up;
+  }
   std::vector<int> order((size_t)n);
   std::vector<double> cost((size_t)n);
   int64_t max_len = 0;
@@ -1073,8 +1098,8 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
         stdecomp_handle* h = hs[i];
         stdk::ChainArgs& a = args[i];
         a = chain_args(h);
-        a.xs = 1;  // (slots of W blocks each: spread placement)
-        a.xid = -1;
+        a.xs = 1;  // (the slot mapping is the queue kernel's)
+        a.xid = local ? 0 : -1;
         a.b_begin = std::min(b0[i] + off, b1[i]);
         a.b_end = std::min(b0[i] + off + kBatchesPerLaunch, b1[i]);
         a.bar = dflags + (size_t)q * W * stdk::kFlagStride;
@@ -1086,8 +1111,10 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
     hipck(hipMemsetAsync(dflags, 0, flag_bytes, h0->stream), "memset");
     hipck(hipMemcpyAsync(dargs, args.data(), sizeof(stdk::ChainArgs) * n, hipMemcpyHostToDevice, h0->stream),
           "batched launch arguments");
-    hipck(stdk::launch_chain_queue(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, h0->mu > 0, dargs, dlist, nslots, W, h0->threads,
-                                   lds, h0->stream),
+    hipck(local ? stdk::launch_chain_queue_xcc(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, dargs, dlist, nslots, W, nx,
+                                               h0->threads, lds, h0->stream)
+                : stdk::launch_chain_queue(h0->s.N == 3, h0->dtype == STD_DTYPE_BF16, h0->mu > 0, dargs, dlist, nslots, W,
+                                           h0->threads, lds, h0->stream),
           "batched chain launch");
     hipck(hipStreamSynchronize(h0->stream), "batched chain launch");  // (args reused next)
     ++launches;
@@ -1109,6 +1136,7 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
                            hipMemcpyDeviceToHost, h0->stream),
             "segment counts");
     hipck(hipStreamSynchronize(h0->stream), "error flag");
+    if (err == 2 && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, kMisplaced);
     if (err && rc == STD_OK) rc = fail(h0, STD_E_DEVICE, "chain workgroup gave up waiting at a grid barrier");
     if (nf != ~0ull && rc == STD_OK) {
       diverged_at(h, h->epoch, nf);
