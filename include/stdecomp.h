@@ -59,12 +59,12 @@ extern "C" {
  * barriers then order memory in that XCC's L2 instead of at device scope, and
  * the values its workgroups exchange stay in L2.  Results are bit-identical
  * either way. */
-#define STD_PLACE_AUTO 0    /* one XCC when W fits one, the core is dense without momentum
-                               and the dispatch was found to deal blocks to the XCCs in
-                               turn, else spread */
+#define STD_PLACE_AUTO 0    /* one XCC when W fits one, the core is dense (r_core = 0) and
+                               the dispatch was found to deal blocks to the XCCs in turn,
+                               else spread */
 #define STD_PLACE_SPREAD 1  /* blocks 0..W-1, spread over the XCCs, device-scope barriers */
 #define STD_PLACE_ONE_XCC 2 /* one XCC, or STD_E_INVAL from stdecomp_init when it cannot
-                               (also with r_core > 0 or momentum > 0) */
+                               (also with r_core > 0) */
 
 typedef struct stdecomp_handle stdecomp_handle;
 
@@ -133,8 +133,8 @@ typedef struct {
                                   is refused (STD_E_INVAL) */
   int32_t placement;           /* STD_PLACE_*: the chain's workgroups on one XCC or spread
                                   (stdecomp_step_batched / stdecomp_epoch_batched put every
-                                  slot on one XCC when every handle of the batch is on one,
-                                  else spread them) */
+                                  slot on one XCC when every handle of the batch is on one
+                                  and none has momentum, else spread them) */
   int32_t reserved[9];         /* must be zero */
 } stdecomp_options;
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libstdecomp.so")
-SOURCES = ["stdecomp_schedule.hip", "stdecomp_chain.hip", "stdecomp_chain_mom.hip", "stdecomp_chain_xcc.hip", "stdecomp_chain_queue_xcc.hip", "stdecomp_eval.hip",
+SOURCES = ["stdecomp_schedule.hip", "stdecomp_chain.hip", "stdecomp_chain_mom.hip", "stdecomp_chain_xcc.hip", "stdecomp_chain_mom_xcc.hip", "stdecomp_chain_queue_xcc.hip", "stdecomp_eval.hip",
            "stdecomp_runtime.hip"]
 ARCH = os.environ.get("STDECOMP_ARCH", "gfx950")
 

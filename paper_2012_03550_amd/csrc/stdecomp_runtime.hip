@@ -86,6 +86,14 @@ struct stdecomp_handle {
 static constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
+namespace stdk {
+// One chain with momentum on one XCC (stdecomp_chain_mom_xcc.hip).
+hipError_t launch_chain_mom_xcc(const ChainArgs& a, int threads, hipStream_t st);
+// Batched chains with every slot on one XCC (stdecomp_chain_queue_xcc.hip).
+hipError_t launch_chain_queue_xcc(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
+                                  int nx, int threads, size_t bytes, hipStream_t st);
+}  // namespace stdk
+
 namespace {
 
 int fail(stdecomp_handle* h, int code, const std::string& msg) {
@@ -144,9 +152,9 @@ int choose_placement(stdecomp_handle* h, int req) {
   h->xs = 1;
   h->xid = -1;
   if (req == STD_PLACE_SPREAD) return STD_OK;
-  if (h->R > 0 || h->mu > 0) {  // (one-XCC kernels exist for the dense core without momentum)
+  if (h->R > 0) {  // (one-XCC kernels exist for the dense core, with and without momentum)
     if (req == STD_PLACE_ONE_XCC)
-      return fail(h, STD_E_INVAL, "placement STD_PLACE_ONE_XCC: not available with the Kruskal core or momentum");
+      return fail(h, STD_E_INVAL, "placement STD_PLACE_ONE_XCC: not available with the Kruskal core");
     return STD_OK;
   }
   int nx = 1;
@@ -896,7 +904,8 @@ int run_range(stdecomp_handle* h, int64_t epoch, int64_t b0, int64_t b1, stdecom
     a.b_begin = c0;
     a.b_end = (c0 + kBatchesPerLaunch < b1) ? c0 + kBatchesPerLaunch : b1;
     HIPCHK(h, hipMemsetAsync(h->bar, 0, (size_t)h->W * stdk::kFlagStride * sizeof(unsigned), h->stream));
-    HIPCHK(h, stdk::launch_chain(a, h->threads, h->stream));
+    HIPCHK(h, (a.mom && a.xid >= 0) ? stdk::launch_chain_mom_xcc(a, h->threads, h->stream)
+                                     : stdk::launch_chain(a, h->threads, h->stream));
     acc->chain_launches++;
   }
   HIPCHK(h, hipEventRecord(h->ev[2], h->stream));
@@ -988,16 +997,6 @@ bool batch_compatible(stdecomp_handle* const* hs, int n, size_t* lds) {
 // the chain's latency-bound minibatch), and a slot runs its chains one after
 // another.  acc[i] receives the work and the launches' time (the whole
 // batched launch for every model).  Errors are reported on hs[0].
-}  // namespace
-
-namespace stdk {
-// Batched chains with every slot on one XCC (stdecomp_chain_queue_xcc.hip).
-hipError_t launch_chain_queue_xcc(int n3, int bf, const ChainArgs* dev_args, const int* dev_list, int nslots, int W,
-                                  int nx, int threads, size_t bytes, hipStream_t st);
-}  // namespace stdk
-
-namespace {
-
 int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std::vector<int64_t>& b0,
                        const std::vector<int64_t>& b1, std::vector<stdecomp_epoch_stats>& acc) {
   stdecomp_handle* h0 = hs[0];
@@ -1005,11 +1004,11 @@ int run_batched_ranges(stdecomp_handle* const* hs, int n, size_t lds, const std:
   if (hipSetDevice(h0->device) != hipSuccess) return fail(h0, STD_E_DEVICE, "hipSetDevice failed");
   int nslots = std::min(n, h0->num_cus / W);
   // every slot on one XCC when every handle is placed on one (dense core, no
-  // momentum, W <= CUs per XCC): nslots a multiple of the XCC count nx, the
+  // momentum in a batch, W <= CUs per XCC): nslots a multiple of the XCC count nx, the
   // slots of one XCC filling at most its CUs
   const int nx = h0->xs;
   bool local = true;
-  for (int i = 0; i < n && local; ++i) local = hs[i]->xid >= 0 && hs[i]->xs == nx;
+  for (int i = 0; i < n && local; ++i) local = hs[i]->xid >= 0 && hs[i]->xs == nx && hs[i]->mu == 0;
   if (local) {
     const int cap = h0->num_cus / W;
     int up = (nslots + nx - 1) / nx * nx;

@@ -49,17 +49,18 @@ def test_auto_places_a_narrow_chain_on_one_xcc(lib):
         assert h.info()["placement"] == SPREAD
 
 
-def test_one_xcc_only_for_the_plain_dense_core(lib):
-    """The one-XCC kernels are those of the dense core without momentum: the
-    Kruskal core and momentum run spread (auto) or are refused (one XCC)."""
+def test_one_xcc_only_for_the_dense_core(lib):
+    """The one-XCC kernels are those of the dense core (with or without
+    momentum): the Kruskal core runs spread (auto) or is refused (one XCC)."""
     dims, ranks = (200, 150, 90), (5, 5, 5)
     idx, vals = synth.random_tiny(3, dims, ranks, 15000, seed=6)
-    for extra in ({"momentum": 0.5}, {"r_core": 3}):
-        with lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, **extra) as h:
-            assert h.info()["placement"] == SPREAD
-        with pytest.raises(lib.StdecompError) as ei:
-            lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, placement="one_xcc", **extra)
-        assert ei.value.code == lib.STD_E_INVAL
+    with lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, r_core=3) as h:
+        assert h.info()["placement"] == SPREAD
+    with pytest.raises(lib.StdecompError) as ei:
+        lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, placement="one_xcc", r_core=3)
+    assert ei.value.code == lib.STD_E_INVAL
+    with lib.Stdecomp(dims, ranks, idx, vals, batch=512, chunk=32, momentum=0.5) as h:
+        assert h.info()["placement"] == ONE_XCC
 
 
 @pytest.mark.parametrize("W", [2, 16, 32])
@@ -83,6 +84,8 @@ CASES = [
     ("n4_j4_bf16_w32", (80, 60, 40, 30), (4, 4, 4, 4), 20000, 2048, 64, "bf16", {}),
     ("n3_mixed_generic_w4", (60, 50, 40), (2, 3, 4), 3000, 32, 8, "f32", {}),
     ("n3_mixed_generic_bf16_w16", (300, 200, 100), (6, 4, 5), 12000, 1024, 64, "bf16", {}),
+    ("n3_j6_momentum_w16", (200, 150, 90), (6, 6, 6), 15000, 512, 32, "f32", {"momentum": 0.5}),
+    ("n4_j4_momentum_bf16_w8", (80, 60, 40, 30), (4, 4, 4, 4), 20000, 512, 64, "bf16", {"momentum": 0.3}),
 ]
 
 
@@ -101,6 +104,9 @@ def test_placements_give_identical_bits(lib, case):
             h.epoch(2)
             A, G = h.get_params()
             res = [a.copy() for a in A] + [G.copy()]
+            if extra.get("momentum"):
+                VA, VG = h.get_velocity()
+                res += [v.copy() for v in VA] + [VG.copy()]
             out[place] = res
     for a, b in zip(out["one_xcc"], out["spread"]):
         assert np.all(np.isfinite(a))
